@@ -1,0 +1,175 @@
+/*
+ * dvbm.h -- C ABI of the MI355X (gfx950) double-distribution quasi-equilibrium
+ * discrete velocity Boltzmann (DDF-QE DVBM) library.
+ *
+ * The library advances the mass/momentum distribution f and the energy
+ * distribution g of Strassle, Hosseini & Karlin, "Consistent kinetic modeling
+ * of compressible flows with variable Prandtl numbers: double-distribution
+ * quasi-equilibrium approach" (arXiv 2510.04197), on a uniform 2-D grid with
+ * the fully discrete update of Eq. (finalDiscretePDE) (Sec. III A 1):
+ *
+ *   X(t+dt) = X - dt/dV sum_faces F_i - dt/tau_1 (X - X*) - dt/tau_2 (X* - X^eq),
+ *   X in {f_i, g_i},
+ *
+ * with Grad-Hermite equilibria and quasi-equilibria (Sec. II D 2-4, Table I,
+ * App. D), the tensor-product Gauss-Hermite velocity sets D2Q16 (total energy
+ * split I) and D2Q25 (internal non-translational energy split II) of App. G,
+ * and NND face values with the generalised van Leer limiter (Sec. III A 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All pointers named "device" are device (HBM) addresses on the current
+ *    HIP device; they are owned by the caller.  The library never allocates
+ *    or frees device memory.  Pointers named "host" are host addresses.
+ *  - Macroscopic fields are dense row-major float64 arrays of ny*nx values,
+ *    element (y, x) at index y*nx + x; cell (y, x) has its centre at
+ *    ((x + 1/2) dx, (y + 1/2) dy).
+ *  - Population buffers use the structure-of-arrays layout
+ *        element (d, i, y, x) at index ((d*Q + i)*ny + y)*pitch + x,
+ *    d = 0 for f and d = 1 for g, pitch = dvbm_pitch(p) elements.
+ *    Population i = a*q1 + b has velocity sqrt(R T_ref) (xi_a, xi_b) and
+ *    weight w_a w_b, with the 1-D Gauss-Hermite nodes xi ascending
+ *    (q1 = 4 for split I, Q = 16; q1 = 5 for split II, Q = 25).
+ *  - Storage DVBM_F64 / DVBM_F32 stores X itself.  DVBM_BF16_DEV /
+ *    DVBM_FP16_DEV store the deviation (X_i - X_ref_i) / w_i rounded to
+ *    nearest-even, where X_ref is the rest equilibrium (rho = 1, u = 0,
+ *    T = T_ref): f_ref_i = w_i; g_ref_i = w_i (Cv - R) T_ref (split II) or
+ *    w_i (Cv T_ref + R T_ref (|xi_i|^2 - 2) / 2) (split I).  F64 computes in
+ *    float64; the other formats compute in float32 with float64 per-node
+ *    moment sums.
+ *  - Every call is asynchronous on the stream given to dvbm_init unless its
+ *    description says it synchronises.
+ *  - Every int-returning call returns DVBM_OK (0) or a negative DVBM_E*
+ *    code; dvbm_last_error() then describes the failure (thread-local).
+ *    A kernel fault surfaces at the next synchronising call as DVBM_EHIP.
+ */
+#ifndef DVBM_H
+#define DVBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DVBM_OK 0
+#define DVBM_EINVAL (-1) /* invalid argument or parameter */
+#define DVBM_EHIP (-2)   /* HIP runtime error (message from hipGetErrorString) */
+#define DVBM_ENAN (-3)   /* non-finite or non-physical state (rho <= 0, T <= 0) */
+#define DVBM_ESTIFF (-4) /* dt / tau_1 > 2 for the initial state */
+
+enum dvbm_storage { DVBM_F64 = 0, DVBM_F32 = 1, DVBM_BF16_DEV = 2, DVBM_FP16_DEV = 3 };
+enum dvbm_bc { DVBM_PERIODIC = 0, DVBM_ZERO_GRADIENT = 1 };
+enum dvbm_visc { DVBM_CONST_MU = 0, DVBM_CONST_TAU = 1 };
+
+/*
+ * Simulation parameters (Sec. III A 3).  dvbm_params_default() fills the
+ * paper's defaults: split II, F32, periodic, CONST_MU, R = 1, gamma = 1.4,
+ * Pr = 0.71, mu = 5e-5 (tau_ref = 5e-5 with p_ref = 1), T_ref = 1,
+ * beta = 1.2, CFL = 0.01, dt = 0 (CFL rule).
+ *
+ * Relaxation times (Sec. II C, Eqs. visc_shear_1 .. Pr_times_cases): the
+ * shear time is tau_nu = tau_ref * p_ref / p(node) for DVBM_CONST_MU (fixed
+ * dynamic viscosity mu = tau_ref * p_ref) or tau_nu = tau_ref for
+ * DVBM_CONST_TAU; tau_alpha = tau_nu / Pr; tau_1 = min, tau_2 = max of the two.
+ */
+typedef struct dvbm_params {
+  int32_t nx, ny;      /* cells, each >= 4 (the flux stencil has radius 2) */
+  int32_t split;       /* 1 = total energy split (D2Q16), 2 = internal non-translational (D2Q25) */
+  int32_t storage;     /* enum dvbm_storage */
+  int32_t bc_x, bc_y;  /* enum dvbm_bc; zero-gradient copies the nearest interior cell into 2 ghost layers */
+  int32_t visc_mode;   /* enum dvbm_visc */
+  int32_t reserved;    /* must be 0 */
+  double dx, dy;       /* cell sizes, > 0 */
+  double R, gamma;     /* gas constant > 0; 1 < gamma <= 2 (split II needs Cv >= D R / 2) */
+  double Pr;           /* Prandtl number > 0 */
+  double tau_ref;      /* > 0, see above */
+  double p_ref;        /* > 0 */
+  double T_ref;        /* lattice reference temperature > 0 */
+  double beta;         /* limiter parameter in [1, 2] */
+  double cfl;          /* > 0; used when dt <= 0 */
+  double dt;           /* > 0 overrides dt = cfl * min(dx, dy) / max(|u| + sqrt(gamma R T)) */
+} dvbm_params;
+
+typedef struct dvbm_handle dvbm_handle;
+
+/* Fill *p with the defaults above (nx = ny = 0: the caller sets the grid). */
+void dvbm_params_default(dvbm_params* p);
+
+/* Number of populations per distribution (16 or 25), or DVBM_EINVAL. */
+int dvbm_num_populations(int32_t split);
+
+/* The library's velocity set (App. G, Tables II-III) for checks: writes Q
+ * velocities to v_host[2*i], v_host[2*i+1] and weights to w_host[i]
+ * (both host arrays of at least 25 entries).  Returns Q or DVBM_EINVAL. */
+int dvbm_velocity_set(int32_t split, double R, double T_ref, double* v_host, double* w_host);
+
+/* Row pitch in elements of the population layout (nx rounded up to 64). */
+int64_t dvbm_pitch(const dvbm_params* p);
+
+/* Bytes of ONE population buffer (f and g) for these parameters; 0 if invalid. */
+size_t dvbm_buffer_bytes(const dvbm_params* p);
+
+/* Bytes of the caller-provided device workspace (reduction partials). */
+size_t dvbm_workspace_bytes(const dvbm_params* p);
+
+/*
+ * Create a solver on two caller-owned device buffers of dvbm_buffer_bytes()
+ * each (ping-pong; 256-byte aligned) and a device workspace of
+ * dvbm_workspace_bytes(), and fill buf0 with the equilibrium populations of
+ * the device float64 fields rho, ux, uy, T (Sec. III A 3: initial conditions
+ * are equilibrium populations).  stream is a hipStream_t (NULL = default).
+ * Computes dt from the fields when p->dt <= 0 (device reduction, then host
+ * arithmetic).  Synchronises.  Errors: EINVAL (parameters, NULL pointers),
+ * ENAN (rho <= 0 or T <= 0 or non-finite input), ESTIFF (dt/tau_1 > 2 at
+ * some node), EHIP.  On success *out owns only host memory.
+ */
+int dvbm_init(const dvbm_params* p, const double* rho, const double* ux, const double* uy,
+              const double* T, void* buf0, void* buf1, void* workspace, void* stream,
+              dvbm_handle** out);
+
+/* Advance nsteps >= 0 time steps of Eq. (finalDiscretePDE) (one fused kernel
+ * launch per step, ping-ponging between the two buffers).  Asynchronous. */
+int dvbm_step(dvbm_handle* h, int64_t nsteps);
+
+/*
+ * Macroscopic fields and global sums of the current state (Eqs.
+ * eq_quadratur1-3).  rho, ux, uy, T: device float64 arrays of ny*nx or NULL.
+ * sums_host (may be NULL): host double[4] = sum over cells of rho, rho ux,
+ * rho uy and total energy E, accumulated in float64 in a fixed order
+ * (deterministic).  Synchronises when sums_host != NULL; returns ENAN if a
+ * sum is not finite.
+ */
+int dvbm_moments(dvbm_handle* h, double* rho, double* ux, double* uy, double* T, double* sums_host);
+
+/* Overwrite the current state with populations given as a dense device
+ * float64 array X[2][Q][ny][nx] (encoded to the storage format). */
+int dvbm_load_populations(dvbm_handle* h, const double* X);
+
+/* Decode the current state into a dense device float64 array X[2][Q][ny][nx]. */
+int dvbm_store_populations(dvbm_handle* h, double* X);
+
+/* Time step in use (host value). */
+double dvbm_get_dt(const dvbm_handle* h);
+
+/* Device address of the buffer holding the current state (buf0 or buf1),
+ * and its index 0/1. */
+void* dvbm_state(const dvbm_handle* h);
+int dvbm_state_index(const dvbm_handle* h);
+
+/* Make buffer index (0 or 1) the current state, e.g. after the caller copied
+ * a checkpoint into it. */
+int dvbm_set_state_index(dvbm_handle* h, int index);
+
+/* Release the handle (host memory only).  NULL is ignored. */
+void dvbm_destroy(dvbm_handle* h);
+
+/* Message describing the last failure on this thread ("" if none). */
+const char* dvbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DVBM_H */

@@ -515,26 +515,43 @@ def diagnostics(f, g, cfg: Config):
 # Single-cell updates on sampled cells (for checks at sizes the full oracle
 # cannot run): the update of a cell needs only a cross of radius 2.
 # --------------------------------------------------------------------------
-def sampled_step(f, g, cfg: Config, dt, ys, xs, tau_ref=None, Pr=None):
-    """One update of the cells ``(ys[k], xs[k])`` of a full state.
-
-    ``f, g`` are ``[Q, ny, nx]`` float64 tensors. Each sample is cut out as a
-    5x5 window (neighbour indices under the configured boundary rules) and the
-    windows are laid side by side in one periodic strip; the centre cell of a
-    window only reads its own window, so its update equals the full update.
-    Returns ``(f_new, g_new)`` of shape ``[Q, S]``.
-    """
-    ys = torch.as_tensor(ys)
-    xs = torch.as_tensor(xs)
+def window_indices(cfg: Config, ys, xs):
+    """Row and column indices ``[S, 5]`` of the radius-2 windows around cells ``(ys, xs)``."""
     off = torch.arange(-2, 3)
-    yi = neighbour(cfg.ny, ys[:, None] + off[None, :], cfg.bc_y)  # [S, 5]
-    xi = neighbour(cfg.nx, xs[:, None] + off[None, :], cfg.bc_x)  # [S, 5]
+    yi = neighbour(cfg.ny, torch.as_tensor(ys)[:, None] + off[None, :], cfg.bc_y)
+    xi = neighbour(cfg.nx, torch.as_tensor(xs)[:, None] + off[None, :], cfg.bc_x)
+    return yi, xi
 
-    def windows(X):
-        W = X[:, yi[:, :, None], xi[:, None, :]]  # [Q, S, 5, 5]
-        return W.permute(0, 2, 1, 3).reshape(X.shape[0], 5, -1)  # [Q, 5, 5S]
 
-    wcfg = Config(**{**cfg.__dict__, "nx": 5 * len(xs), "ny": 5, "bc_x": PERIODIC, "bc_y": PERIODIC})
-    fn, gn = step(windows(f), windows(g), wcfg, dt, tau_ref, Pr)
-    centre = torch.arange(len(xs)) * 5 + 2
+def gather_windows(X: torch.Tensor, yi: torch.Tensor, xi: torch.Tensor) -> torch.Tensor:
+    """``[Q, S, 5, 5]`` windows of ``X`` ([Q, ny, nx]) at the given index sets."""
+    return X[:, yi[:, :, None], xi[:, None, :]]
+
+
+def window_step(fw, gw, cfg: Config, dt, tau_ref=None, Pr=None):
+    """Update of the centre cell of each 5x5 window ``[Q, S, 5, 5]``.
+
+    The update of a cell needs only a cross of radius 2 around it, so the
+    windows are laid side by side in one periodic 5 x 5S strip; each centre
+    reads only its own window. Returns ``(f_new, g_new)`` of shape ``[Q, S]``.
+    """
+    Q, S = fw.shape[:2]
+
+    def strip(W):
+        return W.permute(0, 2, 1, 3).reshape(Q, 5, 5 * S)
+
+    wcfg = Config(**{**cfg.__dict__, "nx": 5 * S, "ny": 5, "bc_x": PERIODIC, "bc_y": PERIODIC})
+    fn, gn = step(strip(fw), strip(gw), wcfg, dt, tau_ref, Pr)
+    centre = torch.arange(S) * 5 + 2
     return fn[:, 2, centre], gn[:, 2, centre]
+
+
+def sampled_step(f, g, cfg: Config, dt, ys, xs, tau_ref=None, Pr=None):
+    """One update of the cells ``(ys[k], xs[k])`` of a full state ``[Q, ny, nx]``.
+
+    Zero-gradient neighbours are taken as clamped indices when the windows
+    are cut out, so the window update equals the full update under either
+    boundary rule.
+    """
+    yi, xi = window_indices(cfg, ys, xs)
+    return window_step(gather_windows(f, yi, xi), gather_windows(g, yi, xi), cfg, dt, tau_ref, Pr)

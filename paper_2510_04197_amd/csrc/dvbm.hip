@@ -1,0 +1,577 @@
+// MI355X (gfx950) implementation of the DDF-QE DVBM hot path and its C ABI.
+//
+// Kernels:
+//   k_collide_advect  one full time step of Eq. (finalDiscretePDE): moments,
+//                     (quasi-)equilibria, two-time relaxation and NND flux
+//                     divergence of every population, fused; one thread per
+//                     cell, populations read once from HBM as coalesced
+//                     structure-of-arrays rows, stencil neighbours through L1/L2.
+//   k_init            equilibrium populations of macroscopic fields (Sec. III A 3).
+//   k_moments         rho, u, T fields and per-block float64 conservation sums.
+//   k_speed           per-block extrema of the initial fields (time step, checks).
+//   k_reduce_*        deterministic final reductions of the per-block partials.
+//   k_encode/k_decode dense float64 populations <-> storage format.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/dvbm.h"
+#include "lattice.h"
+#include "node.h"
+#include "step.h"
+
+namespace dvbm {
+
+constexpr int TX = 64;  // cells per wavefront row (x)
+constexpr int TY = 4;   // wavefront rows per workgroup (y)
+constexpr int RED_BLOCKS = 1024;
+constexpr int RED_THREADS = 256;
+
+// ------------------------------------------------------------ fused step
+template <int SPLIT, class S, int BCX, int BCY, int PRM>
+__global__ __launch_bounds__(TX* TY) void k_collide_advect(const typename S::T* __restrict__ src,
+                                                           typename S::T* __restrict__ dst, KParams kp) {
+  const int x = blockIdx.x * TX + threadIdx.x;
+  const int y = blockIdx.y * TY + threadIdx.y;
+  if (x >= kp.nx || y >= kp.ny) return;
+  cell_update<SPLIT, S, BCX, BCY, PRM>(src, dst, kp, x, y);
+}
+
+// ------------------------------------------------------------ equilibrium initialisation
+template <int SPLIT, class S>
+__global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho, const double* __restrict__ ux,
+                                              const double* __restrict__ uy, const double* __restrict__ T,
+                                              typename S::T* __restrict__ dst, KParams kp) {
+  constexpr int N1 = Set<SPLIT>::N1;
+  constexpr int Q = Set<SPLIT>::Q;
+  const int64_t n = int64_t(kp.nx) * kp.ny;
+  for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < n; c += int64_t(gridDim.x) * blockDim.x) {
+    const int y = int(c / kp.nx), x = int(c % kp.nx);
+    const double r = rho[c], t = T[c];
+    const double isc = 1.0 / sqrt(kp.c2);
+    const double vx = ux[c] * isc, vy = uy[c] * isc;  // normalised velocity
+    const double RT = kp.R * t, th = RT / kp.c2, p = r * RT;
+    const double E = r * kp.Cv * t + 0.5 * r * kp.c2 * (vx * vx + vy * vy);
+    double mx[5], my[5];
+    gauss_hermite_moments(vx, th - 1.0, mx);
+    gauss_hermite_moments(vy, th - 1.0, my);
+    double bf[5][5], bg[3][3];
+    constexpr int NF = Set<SPLIT>::NF;
+    for (int a = 0; a <= NF; ++a)
+      for (int b = 0; a + b <= NF; ++b) bf[a][b] = r * mx[a] * my[b];
+    if (SPLIT == 2) {
+      const double e = r * (kp.Cv - kp.R) * t;
+      for (int a = 0; a <= 2; ++a)
+        for (int b = 0; a + b <= 2; ++b) bg[a][b] = e * mx[a] * my[b];
+    } else {
+      const double diag = (E + p) * th - E;
+      bg[0][0] = E;
+      bg[1][0] = vx * (E + p);
+      bg[0][1] = vy * (E + p);
+      bg[2][0] = (E + 2.0 * p) * vx * vx + diag;
+      bg[1][1] = (E + 2.0 * p) * vx * vy;
+      bg[0][2] = (E + 2.0 * p) * vy * vy + diag;
+    }
+    double f[Q], g[Q];
+    for (int i = 0; i < Q; ++i) f[i] = g[i] = 0.0;
+    expand_add<N1, NF>(bf, f);
+    expand_add<N1, 2>(bg, g);
+    const int64_t off = int64_t(y) * kp.pitch + x;
+    for (int i = 0; i < Q; ++i) {
+      const double w = weight<SPLIT>(i);
+      using C = typename S::C;
+      dst[int64_t(i) * kp.plane + off] = S::enc(C(f[i]), C(1.0 / w), C(1.0));
+      dst[int64_t(Q + i) * kp.plane + off] = S::enc(C(g[i]), C(1.0 / w), C(g_ref_over_w<SPLIT>(kp, i)));
+    }
+  }
+}
+
+// ------------------------------------------------------------ dense <-> storage
+template <int SPLIT, class S>
+__device__ inline double decode_one(const typename S::T v, int d, int i, const KParams& kp) {
+  if (!S::dev) return double(S::raw(v));
+  const double w = weight<SPLIT>(i);
+  const double r = d == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i);
+  return w * (r + double(S::raw(v)));
+}
+
+template <int SPLIT, class S>
+__global__ __launch_bounds__(256) void k_decode(const typename S::T* __restrict__ src, double* __restrict__ X,
+                                                KParams kp) {
+  constexpr int Q = Set<SPLIT>::Q;
+  const int64_t cells = int64_t(kp.nx) * kp.ny, n = 2 * Q * cells;
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x) {
+    const int di = int(k / cells);
+    const int64_t c = k % cells;
+    const int y = int(c / kp.nx), x = int(c % kp.nx);
+    X[k] = decode_one<SPLIT, S>(src[int64_t(di) * kp.plane + int64_t(y) * kp.pitch + x], di / Q, di % Q, kp);
+  }
+}
+
+template <int SPLIT, class S>
+__global__ __launch_bounds__(256) void k_encode(const double* __restrict__ X, typename S::T* __restrict__ dst,
+                                                KParams kp) {
+  constexpr int Q = Set<SPLIT>::Q;
+  using C = typename S::C;
+  const int64_t cells = int64_t(kp.nx) * kp.ny, n = 2 * Q * cells;
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x) {
+    const int di = int(k / cells), d = di / Q, i = di % Q;
+    const int64_t c = k % cells;
+    const int y = int(c / kp.nx), x = int(c % kp.nx);
+    const double w = weight<SPLIT>(i);
+    const double r = d == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i);
+    dst[int64_t(di) * kp.plane + int64_t(y) * kp.pitch + x] = S::enc(C(X[k]), C(1.0 / w), C(r));
+  }
+}
+
+// ------------------------------------------------------------ diagnostics
+// Block tree reduction of 4 doubles (sum or max/min per lane of `mode`).
+__device__ inline void block_reduce4(double (&v)[4], const int (&mode)[4], double* out) {
+  __shared__ double sh[4][RED_THREADS];
+  const int t = threadIdx.x;
+  for (int k = 0; k < 4; ++k) sh[k][t] = v[k];
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      for (int k = 0; k < 4; ++k) {
+        const double a = sh[k][t], b = sh[k][t + s];
+        sh[k][t] = mode[k] == 0 ? a + b : (mode[k] > 0 ? fmax(a, b) : fmin(a, b));
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0)
+    for (int k = 0; k < 4; ++k) out[k] = sh[k][0];
+}
+
+template <int SPLIT, class S>
+__global__ __launch_bounds__(RED_THREADS) void k_moments(const typename S::T* __restrict__ src, KParams kp,
+                                                         double* rho_o, double* ux_o, double* uy_o, double* T_o,
+                                                         double* partials) {
+  constexpr int N1 = Set<SPLIT>::N1;
+  constexpr int Q = Set<SPLIT>::Q;
+  const int64_t n = int64_t(kp.nx) * kp.ny;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const double c = sqrt(kp.c2);
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x) {
+    const int y = int(k / kp.nx), x = int(k % kp.nx);
+    const int64_t off = int64_t(y) * kp.pitch + x;
+    double f[Q], g[Q];
+    for (int i = 0; i < Q; ++i) {
+      f[i] = decode_one<SPLIT, S>(src[int64_t(i) * kp.plane + off], 0, i, kp);
+      g[i] = decode_one<SPLIT, S>(src[int64_t(Q + i) * kp.plane + off], 1, i, kp);
+    }
+    const NodeMoments m = node_moments<N1>(f, g);
+    const double rho = m.rho, jx = c * m.jx, jy = c * m.jy;
+    const double E = SPLIT == 2 ? m.g0 + 0.5 * kp.c2 * (m.pxx + m.pyy) : m.g0;
+    const double ux = jx / rho, uy = jy / rho;
+    const double T = (E / rho - 0.5 * (ux * ux + uy * uy)) * kp.inv_Cv;
+    if (rho_o) rho_o[k] = rho;
+    if (ux_o) ux_o[k] = ux;
+    if (uy_o) uy_o[k] = uy;
+    if (T_o) T_o[k] = T;
+    acc[0] += rho;
+    acc[1] += jx;
+    acc[2] += jy;
+    acc[3] += E;
+  }
+  const int mode[4] = {0, 0, 0, 0};
+  block_reduce4(acc, mode, partials + 4 * blockIdx.x);
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_speed(const double* __restrict__ rho, const double* __restrict__ ux,
+                                                       const double* __restrict__ uy, const double* __restrict__ T,
+                                                       int64_t n, double gR, double R, double* partials) {
+  // lanes: max(|u| + c_s), max(p), -min(rho), -min(T); non-finite input poisons the lane with NaN->+inf
+  double v[4] = {0.0, 0.0, -INFINITY, -INFINITY};
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x) {
+    const double r = rho[k], t = T[k], a = ux[k], b = uy[k];
+    double s = sqrt(a * a + b * b) + sqrt(gR * fmax(t, 0.0));
+    double p = r * R * t;
+    if (!(s == s) || !(p == p) || !isfinite(s) || !isfinite(p)) s = p = INFINITY;
+    v[0] = fmax(v[0], s);
+    v[1] = fmax(v[1], p);
+    v[2] = fmax(v[2], (r == r) ? -r : INFINITY);
+    v[3] = fmax(v[3], (t == t) ? -t : INFINITY);
+  }
+  const int mode[4] = {1, 1, 1, 1};
+  block_reduce4(v, mode, partials + 4 * blockIdx.x);
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_reduce(const double* __restrict__ partials, int nblocks, int modesel,
+                                                        double* out) {
+  double v[4];
+  int mode[4];
+  for (int k = 0; k < 4; ++k) {
+    mode[k] = modesel;
+    v[k] = modesel == 0 ? 0.0 : -INFINITY;
+  }
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+    for (int k = 0; k < 4; ++k) v[k] = modesel == 0 ? v[k] + partials[4 * b + k] : fmax(v[k], partials[4 * b + k]);
+  block_reduce4(v, mode, out);
+}
+
+}  // namespace dvbm
+
+// =================================================================== C ABI
+using namespace dvbm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(DVBM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t _e = (expr);                             \
+    if (_e != hipSuccess) return hip_fail(_e, #expr);   \
+  } while (0)
+
+int storage_bytes(int s) { return s == DVBM_F64 ? 8 : s == DVBM_F32 ? 4 : 2; }
+
+std::string check_params(const dvbm_params* p) {
+  if (!p) return "params is NULL";
+  if (p->nx < 4 || p->ny < 4) return "nx and ny must be >= 4";
+  if (p->split != 1 && p->split != 2) return "split must be 1 or 2";
+  if (p->storage < DVBM_F64 || p->storage > DVBM_FP16_DEV) return "unknown storage";
+  if ((p->bc_x != DVBM_PERIODIC && p->bc_x != DVBM_ZERO_GRADIENT) ||
+      (p->bc_y != DVBM_PERIODIC && p->bc_y != DVBM_ZERO_GRADIENT))
+    return "unknown boundary condition";
+  if (p->visc_mode != DVBM_CONST_MU && p->visc_mode != DVBM_CONST_TAU) return "unknown visc_mode";
+  if (p->reserved != 0) return "reserved must be 0";
+  if (!(p->dx > 0) || !(p->dy > 0)) return "dx, dy must be > 0";
+  if (!(p->R > 0)) return "R must be > 0";
+  if (!(p->gamma > 1.0) || !(p->gamma <= 2.0)) return "gamma must lie in (1, 2] (Cv >= D R / 2)";
+  if (!(p->Pr > 0)) return "Pr must be > 0";
+  if (!(p->tau_ref > 0) || !(p->p_ref > 0) || !(p->T_ref > 0)) return "tau_ref, p_ref, T_ref must be > 0";
+  if (!(p->beta >= 1.0) || !(p->beta <= 2.0)) return "beta must lie in [1, 2]";
+  if (!(p->dt > 0) && !(p->cfl > 0)) return "cfl must be > 0 when dt <= 0";
+  if (!std::isfinite(p->dt)) return "dt must be finite";
+  const double nmax = 2147483647.0;
+  if (double(p->nx) * double(p->ny) > nmax) return "nx * ny too large";
+  return "";
+}
+
+int pr_mode(double Pr) { return Pr == 1.0 ? PR_UNIT : (Pr < 1.0 ? PR_LOW : PR_HIGH); }
+
+}  // namespace
+
+struct dvbm_handle {
+  dvbm_params p;
+  KParams kp;
+  int Q;
+  void* buf[2];
+  int cur;
+  double* ws;
+  hipStream_t stream;
+  double dt;
+};
+
+namespace {
+
+KParams make_kparams(const dvbm_params& p, double dt) {
+  KParams k;
+  k.nx = p.nx;
+  k.ny = p.ny;
+  k.pitch = dvbm_pitch(&p);
+  k.plane = k.pitch * p.ny;
+  k.c2 = p.R * p.T_ref;
+  k.R = p.R;
+  k.Cv = p.R / (p.gamma - 1.0);
+  k.inv_Cv = 1.0 / k.Cv;
+  const double c = std::sqrt(k.c2);
+  k.kx = dt * c / p.dx;
+  k.ky = dt * c / p.dy;
+  k.const_mu = p.visc_mode == DVBM_CONST_MU;
+  k.om_scale = k.const_mu ? dt / (p.tau_ref * p.p_ref) : dt / p.tau_ref;
+  k.Pr = p.Pr;
+  k.beta2 = 2.0 * p.beta;
+  if (p.split == 2) {
+    k.gr0 = (k.Cv - p.R) * p.T_ref;
+    k.gr1 = 0.0;
+  } else {
+    k.gr0 = k.Cv * p.T_ref;
+    k.gr1 = 0.5 * k.c2;
+  }
+  return k;
+}
+
+template <int SPLIT, class S, int BCX, int BCY>
+void launch_step_bc(const dvbm_handle* h, const void* src, void* dst) {
+  using T = typename S::T;
+  const dim3 block(TX, TY);
+  const dim3 grid((h->p.nx + TX - 1) / TX, (h->p.ny + TY - 1) / TY);
+  const int prm = pr_mode(h->p.Pr);
+  const T* s = static_cast<const T*>(src);
+  T* d = static_cast<T*>(dst);
+  if (prm == PR_UNIT)
+    hipLaunchKernelGGL((k_collide_advect<SPLIT, S, BCX, BCY, PR_UNIT>), grid, block, 0, h->stream, s, d, h->kp);
+  else if (prm == PR_LOW)
+    hipLaunchKernelGGL((k_collide_advect<SPLIT, S, BCX, BCY, PR_LOW>), grid, block, 0, h->stream, s, d, h->kp);
+  else
+    hipLaunchKernelGGL((k_collide_advect<SPLIT, S, BCX, BCY, PR_HIGH>), grid, block, 0, h->stream, s, d, h->kp);
+}
+
+template <int SPLIT, class S>
+void launch_step_s(const dvbm_handle* h, const void* src, void* dst) {
+  const int bx = h->p.bc_x, by = h->p.bc_y;
+  if (bx == DVBM_PERIODIC && by == DVBM_PERIODIC)
+    launch_step_bc<SPLIT, S, BC_PERIODIC, BC_PERIODIC>(h, src, dst);
+  else if (bx == DVBM_ZERO_GRADIENT && by == DVBM_PERIODIC)
+    launch_step_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_PERIODIC>(h, src, dst);
+  else if (bx == DVBM_PERIODIC && by == DVBM_ZERO_GRADIENT)
+    launch_step_bc<SPLIT, S, BC_PERIODIC, BC_ZERO_GRADIENT>(h, src, dst);
+  else
+    launch_step_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_ZERO_GRADIENT>(h, src, dst);
+}
+
+// Calls F<SPLIT, Store>::run(args...) for the handle's split and storage.
+template <template <int, class> class F, class... A>
+void dispatch(const dvbm_params& p, A&&... args) {
+  if (p.split == 2) {
+    switch (p.storage) {
+      case DVBM_F64: F<2, StoreF64>::run(args...); break;
+      case DVBM_F32: F<2, StoreF32>::run(args...); break;
+      case DVBM_BF16_DEV: F<2, StoreBF16>::run(args...); break;
+      default: F<2, StoreF16>::run(args...); break;
+    }
+  } else {
+    switch (p.storage) {
+      case DVBM_F64: F<1, StoreF64>::run(args...); break;
+      case DVBM_F32: F<1, StoreF32>::run(args...); break;
+      case DVBM_BF16_DEV: F<1, StoreBF16>::run(args...); break;
+      default: F<1, StoreF16>::run(args...); break;
+    }
+  }
+}
+
+template <int SPLIT, class S>
+struct StepOp {
+  static void run(const dvbm_handle* h, const void* src, void* dst) { launch_step_s<SPLIT, S>(h, src, dst); }
+};
+
+template <int SPLIT, class S>
+struct InitOp {
+  static void run(const dvbm_handle* h, const double* rho, const double* ux, const double* uy, const double* T,
+                  void* dst) {
+    using Tt = typename S::T;
+    hipLaunchKernelGGL((k_init<SPLIT, S>), dim3(RED_BLOCKS * 4), dim3(256), 0, h->stream, rho, ux, uy, T,
+                       static_cast<Tt*>(dst), h->kp);
+  }
+};
+
+template <int SPLIT, class S>
+struct MomentsOp {
+  static void run(const dvbm_handle* h, const void* src, double* rho, double* ux, double* uy, double* T,
+                  double* partials) {
+    using Tt = typename S::T;
+    hipLaunchKernelGGL((k_moments<SPLIT, S>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, h->stream,
+                       static_cast<const Tt*>(src), h->kp, rho, ux, uy, T, partials);
+  }
+};
+
+template <int SPLIT, class S>
+struct DecodeOp {
+  static void run(const dvbm_handle* h, const void* src, double* X) {
+    using Tt = typename S::T;
+    hipLaunchKernelGGL((k_decode<SPLIT, S>), dim3(RED_BLOCKS * 4), dim3(256), 0, h->stream,
+                       static_cast<const Tt*>(src), X, h->kp);
+  }
+};
+
+template <int SPLIT, class S>
+struct EncodeOp {
+  static void run(const dvbm_handle* h, const double* X, void* dst) {
+    using Tt = typename S::T;
+    hipLaunchKernelGGL((k_encode<SPLIT, S>), dim3(RED_BLOCKS * 4), dim3(256), 0, h->stream, X,
+                       static_cast<Tt*>(dst), h->kp);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+void dvbm_params_default(dvbm_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->split = 2;
+  p->storage = DVBM_F32;
+  p->bc_x = p->bc_y = DVBM_PERIODIC;
+  p->visc_mode = DVBM_CONST_MU;
+  p->dx = p->dy = 1.0;
+  p->R = 1.0;
+  p->gamma = 1.4;
+  p->Pr = 0.71;
+  p->tau_ref = 5e-5;
+  p->p_ref = 1.0;
+  p->T_ref = 1.0;
+  p->beta = 1.2;
+  p->cfl = 0.01;
+  p->dt = 0.0;
+}
+
+int dvbm_num_populations(int32_t split) {
+  if (split == 1) return 16;
+  if (split == 2) return 25;
+  return fail(DVBM_EINVAL, "split must be 1 or 2");
+}
+
+int dvbm_velocity_set(int32_t split, double R, double T_ref, double* v, double* w) {
+  if ((split != 1 && split != 2) || !v || !w || !(R > 0) || !(T_ref > 0))
+    return fail(DVBM_EINVAL, "dvbm_velocity_set: bad argument");
+  const double c = std::sqrt(R * T_ref);
+  const int n1 = split == 1 ? 4 : 5;
+  for (int a = 0; a < n1; ++a)
+    for (int b = 0; b < n1; ++b) {
+      const int i = a * n1 + b;
+      const double xa = split == 1 ? GH<4>::xi(a) : GH<5>::xi(a);
+      const double xb = split == 1 ? GH<4>::xi(b) : GH<5>::xi(b);
+      const double wa = split == 1 ? GH<4>::w(a) : GH<5>::w(a);
+      const double wb = split == 1 ? GH<4>::w(b) : GH<5>::w(b);
+      v[2 * i] = c * xa;
+      v[2 * i + 1] = c * xb;
+      w[i] = wa * wb;
+    }
+  return n1 * n1;
+}
+
+int64_t dvbm_pitch(const dvbm_params* p) {
+  if (!p || p->nx <= 0) return 0;
+  return (int64_t(p->nx) + 63) / 64 * 64;
+}
+
+size_t dvbm_buffer_bytes(const dvbm_params* p) {
+  if (!check_params(p).empty()) return 0;
+  const int Q = p->split == 1 ? 16 : 25;
+  return size_t(2) * Q * size_t(p->ny) * size_t(dvbm_pitch(p)) * storage_bytes(p->storage);
+}
+
+size_t dvbm_workspace_bytes(const dvbm_params* p) {
+  (void)p;
+  return size_t(RED_BLOCKS * 4 + 64) * sizeof(double);
+}
+
+int dvbm_init(const dvbm_params* p, const double* rho, const double* ux, const double* uy, const double* T,
+              void* buf0, void* buf1, void* workspace, void* stream, dvbm_handle** out) {
+  g_last_error.clear();
+  const std::string err = check_params(p);
+  if (!err.empty()) return fail(DVBM_EINVAL, "dvbm_init: " + err);
+  if (!rho || !ux || !uy || !T || !buf0 || !buf1 || !workspace || !out)
+    return fail(DVBM_EINVAL, "dvbm_init: NULL pointer argument");
+  if ((reinterpret_cast<uintptr_t>(buf0) | reinterpret_cast<uintptr_t>(buf1)) & 255u)
+    return fail(DVBM_EINVAL, "dvbm_init: population buffers must be 256-byte aligned");
+  if (buf0 == buf1) return fail(DVBM_EINVAL, "dvbm_init: buf0 and buf1 must differ");
+  *out = nullptr;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* ws = static_cast<double*>(workspace);
+  const int64_t n = int64_t(p->nx) * p->ny;
+
+  // extrema of the initial fields: time step (Sec. III A 3) and validity
+  hipLaunchKernelGGL(k_speed, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, rho, ux, uy, T, n, p->gamma * p->R, p->R,
+                     ws);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, s, ws, RED_BLOCKS, 1, ws + 4 * RED_BLOCKS);
+  HIP_TRY(hipGetLastError());
+  double ext[4];
+  HIP_TRY(hipMemcpyAsync(ext, ws + 4 * RED_BLOCKS, sizeof(ext), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const double smax = ext[0], pmax = ext[1], rmin = -ext[2], tmin = -ext[3];
+  if (!std::isfinite(smax) || !std::isfinite(pmax) || !(rmin > 0) || !(tmin > 0))
+    return fail(DVBM_ENAN, "dvbm_init: initial fields must be finite with rho > 0 and T > 0");
+  const double dt = p->dt > 0 ? p->dt : p->cfl * std::fmin(p->dx, p->dy) / smax;
+
+  // stiffness: omega_1 = dt / tau_1 must stay <= 2 (explicit Euler relaxation)
+  const double om_nu = p->visc_mode == DVBM_CONST_MU ? dt * pmax / (p->tau_ref * p->p_ref) : dt / p->tau_ref;
+  const double om1 = p->Pr > 1.0 ? om_nu * p->Pr : om_nu;
+  if (om1 > 2.0)
+    return fail(DVBM_ESTIFF, "dvbm_init: dt / tau_1 = " + std::to_string(om1) + " > 2 for the initial state");
+
+  dvbm_handle* h = new dvbm_handle;
+  h->p = *p;
+  h->dt = dt;
+  h->kp = make_kparams(*p, dt);
+  h->Q = p->split == 1 ? 16 : 25;
+  h->buf[0] = buf0;
+  h->buf[1] = buf1;
+  h->cur = 0;
+  h->ws = ws;
+  h->stream = s;
+  dispatch<InitOp>(h->p, h, rho, ux, uy, T, buf0);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "dvbm_init: equilibrium initialisation");
+  }
+  *out = h;
+  return DVBM_OK;
+}
+
+int dvbm_step(dvbm_handle* h, int64_t nsteps) {
+  if (!h) return fail(DVBM_EINVAL, "dvbm_step: NULL handle");
+  if (nsteps < 0) return fail(DVBM_EINVAL, "dvbm_step: nsteps < 0");
+  for (int64_t k = 0; k < nsteps; ++k) {
+    dispatch<StepOp>(h->p, h, h->buf[h->cur], h->buf[1 - h->cur]);
+    h->cur ^= 1;
+  }
+  HIP_TRY(hipGetLastError());
+  return DVBM_OK;
+}
+
+int dvbm_moments(dvbm_handle* h, double* rho, double* ux, double* uy, double* T, double* sums_host) {
+  if (!h) return fail(DVBM_EINVAL, "dvbm_moments: NULL handle");
+  dispatch<MomentsOp>(h->p, h, h->buf[h->cur], rho, ux, uy, T, h->ws);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, h->stream, h->ws, RED_BLOCKS, 0,
+                     h->ws + 4 * RED_BLOCKS);
+  HIP_TRY(hipGetLastError());
+  if (sums_host) {
+    HIP_TRY(hipMemcpyAsync(sums_host, h->ws + 4 * RED_BLOCKS, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int k = 0; k < 4; ++k)
+      if (!std::isfinite(sums_host[k])) return fail(DVBM_ENAN, "dvbm_moments: non-finite conservation sum");
+  }
+  return DVBM_OK;
+}
+
+int dvbm_load_populations(dvbm_handle* h, const double* X) {
+  if (!h || !X) return fail(DVBM_EINVAL, "dvbm_load_populations: NULL argument");
+  dispatch<EncodeOp>(h->p, h, X, h->buf[h->cur]);
+  HIP_TRY(hipGetLastError());
+  return DVBM_OK;
+}
+
+int dvbm_store_populations(dvbm_handle* h, double* X) {
+  if (!h || !X) return fail(DVBM_EINVAL, "dvbm_store_populations: NULL argument");
+  dispatch<DecodeOp>(h->p, h, h->buf[h->cur], X);
+  HIP_TRY(hipGetLastError());
+  return DVBM_OK;
+}
+
+double dvbm_get_dt(const dvbm_handle* h) { return h ? h->dt : 0.0; }
+
+void* dvbm_state(const dvbm_handle* h) { return h ? h->buf[h->cur] : nullptr; }
+
+int dvbm_state_index(const dvbm_handle* h) { return h ? h->cur : fail(DVBM_EINVAL, "NULL handle"); }
+
+int dvbm_set_state_index(dvbm_handle* h, int index) {
+  if (!h || (index != 0 && index != 1)) return fail(DVBM_EINVAL, "dvbm_set_state_index: bad argument");
+  h->cur = index;
+  return DVBM_OK;
+}
+
+void dvbm_destroy(dvbm_handle* h) { delete h; }
+
+const char* dvbm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,222 @@
+"""ctypes binding of the DDF-QE DVBM C ABI (``include/dvbm.h``).
+
+Argument marshalling only: every computation runs in the HIP kernels of
+``libdvbm.so``. PyTorch supplies device memory (the two population buffers
+and the workspace are ``torch.uint8`` tensors) and the HIP stream. Loading
+fails loudly when the built library is missing.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libdvbm.so")
+
+DVBM_OK = 0
+DVBM_EINVAL = -1
+DVBM_EHIP = -2
+DVBM_ENAN = -3
+DVBM_ESTIFF = -4
+
+STORAGE = {"f64": 0, "f32": 1, "bf16_dev": 2, "fp16_dev": 3}
+BC = {"periodic": 0, "zero_gradient": 1}
+VISC = {"const_mu": 0, "const_tau": 1}
+
+# every symbol declared in include/dvbm.h, with (restype, argtypes)
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("split", ctypes.c_int32),
+        ("storage", ctypes.c_int32), ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+        ("visc_mode", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("dx", _D), ("dy", _D), ("R", _D), ("gamma", _D), ("Pr", _D), ("tau_ref", _D),
+        ("p_ref", _D), ("T_ref", _D), ("beta", _D), ("cfl", _D), ("dt", _D),
+    ]
+
+
+_PP = ctypes.POINTER(Params)
+
+SIGNATURES = {
+    "dvbm_params_default": (None, [_PP]),
+    "dvbm_num_populations": (ctypes.c_int, [ctypes.c_int32]),
+    "dvbm_velocity_set": (ctypes.c_int, [ctypes.c_int32, _D, _D, _DP, _DP]),
+    "dvbm_pitch": (ctypes.c_int64, [_PP]),
+    "dvbm_buffer_bytes": (ctypes.c_size_t, [_PP]),
+    "dvbm_workspace_bytes": (ctypes.c_size_t, [_PP]),
+    "dvbm_init": (ctypes.c_int, [_PP, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
+    "dvbm_step": (ctypes.c_int, [_P, ctypes.c_int64]),
+    "dvbm_moments": (ctypes.c_int, [_P, _P, _P, _P, _P, _DP]),
+    "dvbm_load_populations": (ctypes.c_int, [_P, _P]),
+    "dvbm_store_populations": (ctypes.c_int, [_P, _P]),
+    "dvbm_get_dt": (_D, [_P]),
+    "dvbm_state": (_P, [_P]),
+    "dvbm_state_index": (ctypes.c_int, [_P]),
+    "dvbm_set_state_index": (ctypes.c_int, [_P, ctypes.c_int]),
+    "dvbm_destroy": (None, [_P]),
+    "dvbm_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+class DVBMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dvbm error {code}: {msg}")
+        self.code = code
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load ``libdvbm.so`` and declare its signatures; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2510_04197_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != DVBM_OK:
+        raise DVBMError(code, _lib.dvbm_last_error().decode())
+    return code
+
+
+def num_populations(split: int) -> int:
+    return 16 if split == 1 else 25
+
+
+def make_params(nx, ny, split=2, storage="f32", bc_x="periodic", bc_y="periodic", visc_mode="const_mu",
+                dx=None, dy=None, R=1.0, gamma=1.4, Pr=0.71, tau_ref=5e-5, p_ref=1.0, T_ref=1.0,
+                beta=1.2, cfl=0.01, dt=0.0) -> Params:
+    lib = load_library()
+    p = Params()
+    lib.dvbm_params_default(ctypes.byref(p))
+    p.nx, p.ny, p.split = int(nx), int(ny), int(split)
+    p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    p.bc_x = BC[bc_x] if isinstance(bc_x, str) else int(bc_x)
+    p.bc_y = BC[bc_y] if isinstance(bc_y, str) else int(bc_y)
+    p.visc_mode = VISC[visc_mode] if isinstance(visc_mode, str) else int(visc_mode)
+    p.dx = float(dx if dx is not None else 1.0 / nx)
+    p.dy = float(dy if dy is not None else p.dx)
+    p.R, p.gamma, p.Pr, p.tau_ref, p.p_ref, p.T_ref = map(float, (R, gamma, Pr, tau_ref, p_ref, T_ref))
+    p.beta, p.cfl, p.dt = float(beta), float(cfl), float(dt)
+    return p
+
+
+def velocity_set(split: int, R: float = 1.0, T_ref: float = 1.0):
+    lib = load_library()
+    v = (ctypes.c_double * 50)()
+    w = (ctypes.c_double * 25)()
+    q = lib.dvbm_velocity_set(split, R, T_ref, v, w)
+    if q < 0:
+        _check(q)
+    return np.array(v[: 2 * q]).reshape(q, 2), np.array(w[:q])
+
+
+def _dev_f64(a, device):
+    t = torch.as_tensor(a, dtype=torch.float64, device=device)
+    return t.contiguous()
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One DDF-QE DVBM simulation on one GPU (a handle plus its torch-owned buffers)."""
+
+    def __init__(self, params: Params, rho, ux, uy, T, device="cuda", stream: torch.cuda.Stream | None = None):
+        self.lib = load_library()
+        self.params = params
+        self.device = torch.device(device)
+        self.Q = num_populations(params.split)
+        nbytes = self.lib.dvbm_buffer_bytes(ctypes.byref(params))
+        if nbytes == 0:
+            raise DVBMError(DVBM_EINVAL, "invalid parameters")
+        wbytes = self.lib.dvbm_workspace_bytes(ctypes.byref(params))
+        self.buffers = [torch.empty(nbytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        self.workspace = torch.empty(wbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        fields = [_dev_f64(a, self.device) for a in (rho, ux, uy, T)]
+        for f in fields:
+            if tuple(f.shape) != (params.ny, params.nx):
+                raise ValueError(f"fields must have shape (ny, nx) = {(params.ny, params.nx)}")
+        self._fields0 = fields  # keep alive until the handle has used them
+        h = ctypes.c_void_p()
+        _check(self.lib.dvbm_init(ctypes.byref(params), *[_ptr(f) for f in fields], _ptr(self.buffers[0]),
+                                  _ptr(self.buffers[1]), _ptr(self.workspace),
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+
+    # ------------------------------------------------------------------ stepping
+    def step(self, nsteps: int = 1):
+        _check(self.lib.dvbm_step(self.handle, int(nsteps)))
+
+    @property
+    def dt(self) -> float:
+        return float(self.lib.dvbm_get_dt(self.handle))
+
+    @property
+    def state_index(self) -> int:
+        return int(self.lib.dvbm_state_index(self.handle))
+
+    def set_state_index(self, idx: int):
+        _check(self.lib.dvbm_set_state_index(self.handle, int(idx)))
+
+    @property
+    def state_buffer(self) -> torch.Tensor:
+        return self.buffers[self.state_index]
+
+    # ------------------------------------------------------------------ diagnostics
+    def moments(self, fields: bool = True, sums: bool = True):
+        ny, nx = self.params.ny, self.params.nx
+        out = {}
+        if fields:
+            for k in ("rho", "ux", "uy", "T"):
+                out[k] = torch.empty((ny, nx), dtype=torch.float64, device=self.device)
+        ptrs = [_ptr(out[k]) if fields else None for k in ("rho", "ux", "uy", "T")]
+        s = (ctypes.c_double * 4)()
+        _check(self.lib.dvbm_moments(self.handle, *ptrs, s if sums else None))
+        if sums:
+            out["sums"] = np.array(s[:])
+        return out
+
+    def load_populations(self, X: torch.Tensor):
+        """Overwrite the current state from a dense float64 ``[2, Q, ny, nx]`` tensor."""
+        X = _dev_f64(X, self.device)
+        if tuple(X.shape) != (2, self.Q, self.params.ny, self.params.nx):
+            raise ValueError("populations must have shape (2, Q, ny, nx)")
+        _check(self.lib.dvbm_load_populations(self.handle, _ptr(X)))
+        self.stream.synchronize()
+
+    def store_populations(self) -> torch.Tensor:
+        X = torch.empty((2, self.Q, self.params.ny, self.params.nx), dtype=torch.float64, device=self.device)
+        _check(self.lib.dvbm_store_populations(self.handle, _ptr(X)))
+        self.stream.synchronize()
+        return X
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.dvbm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,87 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+symbol, and its host-only entry points behave (no GPU needed)."""
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dvbm.h")
+LIB = os.path.join(ROOT, "paper_2510_04197_amd", "libdvbm.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libdvbm.so not built")
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dvbm_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(LIB)
+    names = declared_symbols()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_declares_every_symbol():
+    from paper_2510_04197_amd import dvbm
+    assert set(declared_symbols()) == set(dvbm.SIGNATURES)
+
+
+@pytest.mark.parametrize("split,n1", ((1, 4), (2, 5)))
+def test_library_velocity_set_matches_numpy_quadrature(split, n1):
+    from paper_2510_04197_amd import velocity_set
+    v, w = velocity_set(split, R=1.3, T_ref=0.7)
+    x, wx = np.polynomial.hermite_e.hermegauss(n1)
+    wx = wx / math.sqrt(2 * math.pi)
+    c = math.sqrt(1.3 * 0.7)
+    np.testing.assert_allclose(v[:, 0], c * np.repeat(x, n1), atol=1e-14)
+    np.testing.assert_allclose(v[:, 1], c * np.tile(x, n1), atol=1e-14)
+    np.testing.assert_allclose(w, np.repeat(wx, n1) * np.tile(wx, n1), rtol=1e-13)
+
+
+def test_sizes_and_defaults():
+    from paper_2510_04197_amd import dvbm
+    lib = dvbm.load_library()
+    p = dvbm.make_params(100, 30, split=2, storage="f32")
+    assert lib.dvbm_pitch(ctypes.byref(p)) == 128
+    assert lib.dvbm_buffer_bytes(ctypes.byref(p)) == 2 * 25 * 30 * 128 * 4
+    p16 = dvbm.make_params(100, 30, split=1, storage="bf16_dev")
+    assert lib.dvbm_buffer_bytes(ctypes.byref(p16)) == 2 * 16 * 30 * 128 * 2
+    d = dvbm.Params()
+    lib.dvbm_params_default(ctypes.byref(d))
+    assert (d.split, d.gamma, d.Pr, d.beta, d.cfl, d.tau_ref) == (2, 1.4, 0.71, 1.2, 0.01, 5e-5)
+    assert lib.dvbm_num_populations(1) == 16 and lib.dvbm_num_populations(2) == 25
+    assert lib.dvbm_num_populations(3) == dvbm.DVBM_EINVAL
+
+
+@pytest.mark.parametrize("field,value", [("nx", 3), ("split", 3), ("gamma", 2.5), ("beta", 0.9), ("Pr", 0.0),
+                                         ("storage", 7), ("tau_ref", -1.0), ("reserved", 1)])
+def test_invalid_parameters_rejected_before_any_device_work(field, value):
+    from paper_2510_04197_amd import dvbm
+    lib = dvbm.load_library()
+    p = dvbm.make_params(16, 16)
+    setattr(p, field, value)
+    assert lib.dvbm_buffer_bytes(ctypes.byref(p)) == 0
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(256)
+    rc = lib.dvbm_init(ctypes.byref(p), dummy, dummy, dummy, dummy, dummy, ctypes.c_void_p(512), dummy, None,
+                       ctypes.byref(h))
+    assert rc == dvbm.DVBM_EINVAL
+    assert lib.dvbm_last_error().decode().startswith("dvbm_init:")
+
+
+def test_null_handle_calls_fail_cleanly():
+    from paper_2510_04197_amd import dvbm
+    lib = dvbm.load_library()
+    assert lib.dvbm_step(None, 1) == dvbm.DVBM_EINVAL
+    assert lib.dvbm_moments(None, None, None, None, None, None) == dvbm.DVBM_EINVAL
+    assert lib.dvbm_set_state_index(None, 0) == dvbm.DVBM_EINVAL
+    lib.dvbm_destroy(None)

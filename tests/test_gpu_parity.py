@@ -1,0 +1,274 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (relative L2 over all populations of both distributions):
+* float64 storage: 1e-12 for the state and, to make the comparison sensitive
+  to the update itself, 1e-9 on the increment X(t+n dt) - X(t);
+* float32 storage (float32 arithmetic, float64 moment sums): 1e-5;
+* 16-bit deviation storage: the final rounding of (X - X_ref)/w dominates,
+  so the bound is the format's unit roundoff (2^-8 bfloat16, 2^-11 half)
+  times the norm of the deviation, plus float32 arithmetic.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import dvbm_oracle as O
+from paper_2510_04197_amd import DVBMError, Solver, dvbm, make_params
+from synth import isentropic_vortex, shear_wave, shock_vortex, smooth_random, thermal_wave, uniform
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def oracle_cfg(p) -> O.Config:
+    inv_bc = {0: O.PERIODIC, 1: O.ZERO_GRADIENT}
+    return O.Config(nx=p.nx, ny=p.ny, split=p.split, bc_x=inv_bc[p.bc_x], bc_y=inv_bc[p.bc_y],
+                    visc_mode=O.CONST_MU if p.visc_mode == 0 else O.CONST_TAU, dx=p.dx, dy=p.dy, R=p.R,
+                    gamma=p.gamma, Pr=p.Pr, tau_ref=p.tau_ref, p_ref=p.p_ref, T_ref=p.T_ref, beta=p.beta,
+                    cfl=p.cfl)
+
+
+def solver(wl, **kw):
+    p = make_params(wl.nx, wl.ny, dx=wl.dx, dy=wl.dy, **kw)
+    return Solver(p, wl.rho, wl.ux, wl.uy, wl.T, device=DEV), p
+
+
+def rel(a, b):
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def oracle_state(s: Solver):
+    X = s.store_populations().cpu()
+    return X[0], X[1]
+
+
+# ---------------------------------------------------------------- initial state
+@pytest.mark.parametrize("split", (1, 2))
+@pytest.mark.parametrize("storage,tol", (("f64", 1e-14), ("f32", 1e-7)))
+def test_initial_equilibrium(split, storage, tol):
+    wl = smooth_random(70, 37, seed=1)
+    s, p = solver(wl, split=split, storage=storage, tau_ref=0.02)
+    f, g = oracle_state(s)
+    fo, go = O.initial_state(wl.rho, wl.ux, wl.uy, wl.T, oracle_cfg(p))
+    assert rel(f, fo) < tol and rel(g, go) < tol
+
+
+# ---------------------------------------------------------------- multi-step parity, small grids
+CASES = [(split, Pr, bc) for split in (1, 2) for Pr in (0.5, 1.0, 2.0) for bc in ("periodic", "zero_gradient")]
+
+
+@pytest.mark.parametrize("split,Pr,bc", CASES)
+def test_steps_fp64(split, Pr, bc):
+    wl = smooth_random(70, 37, seed=2)  # two 64-wide tiles in x with a ragged tail, ragged rows in y
+    s, p = solver(wl, split=split, storage="f64", Pr=Pr, tau_ref=0.02, bc_x=bc, cfl=0.1)
+    cfg = oracle_cfg(p)
+    f0, g0 = O.initial_state(wl.rho, wl.ux, wl.uy, wl.T, cfg)
+    s.step(8)
+    f, g = oracle_state(s)
+    fo, go = O.run(f0, g0, cfg, s.dt, 8)
+    assert rel(f, fo) < 1e-12 and rel(g, go) < 1e-12
+    assert rel(f - f0, fo - f0) < 1e-9 and rel(g - g0, go - g0) < 1e-9
+
+
+@pytest.mark.parametrize("split,Pr,bc", CASES)
+def test_steps_fp32(split, Pr, bc):
+    wl = smooth_random(70, 37, seed=3)
+    s, p = solver(wl, split=split, storage="f32", Pr=Pr, tau_ref=0.02, bc_x=bc, bc_y=bc, cfl=0.1)
+    cfg = oracle_cfg(p)
+    f0, g0 = O.initial_state(wl.rho, wl.ux, wl.uy, wl.T, cfg)
+    s.step(8)
+    f, g = oracle_state(s)
+    fo, go = O.run(f0, g0, cfg, s.dt, 8)
+    assert rel(f, fo) < 1e-5 and rel(g, go) < 1e-5
+
+
+@pytest.mark.parametrize("mode", ("const_mu", "const_tau"))
+def test_off_equilibrium_single_step_fp64(mode):
+    """One step from a perturbed (non-equilibrium) state loaded through the ABI."""
+    wl = smooth_random(67, 9, seed=4)
+    s, p = solver(wl, split=2, storage="f64", Pr=0.6, tau_ref=0.02, visc_mode=mode, R=1.1, T_ref=0.9,
+                  gamma=1.3, dt=2e-4)
+    cfg = oracle_cfg(p)
+    f0, g0 = O.initial_state(wl.rho, wl.ux, wl.uy, wl.T, cfg)
+    rng = np.random.default_rng(0)
+    f0 = f0 * (1 + 0.01 * torch.tensor(rng.standard_normal(f0.shape)))
+    g0 = g0 * (1 + 0.01 * torch.tensor(rng.standard_normal(g0.shape)))
+    s.load_populations(torch.stack([f0, g0]))
+    s.step(1)
+    f, g = oracle_state(s)
+    fo, go = O.step(f0, g0, cfg, 2e-4)
+    assert rel(f - f0, fo - f0) < 1e-10 and rel(g - g0, go - g0) < 1e-10
+
+
+def test_minimal_grid():
+    wl = smooth_random(4, 4, seed=5)
+    s, p = solver(wl, split=2, storage="f64", tau_ref=0.02, cfl=0.1)
+    cfg = oracle_cfg(p)
+    f0, g0 = O.initial_state(wl.rho, wl.ux, wl.uy, wl.T, cfg)
+    s.step(3)
+    f, g = oracle_state(s)
+    fo, go = O.run(f0, g0, cfg, s.dt, 3)
+    assert rel(f, fo) < 1e-12 and rel(g, go) < 1e-12
+
+
+# ---------------------------------------------------------------- the 64^2 shear-wave workload, 1000 steps
+def test_shear_wave_64_fp64_1000_steps():
+    """64^2 periodic shear wave (u_y = 1e-3 sin, Ma = 0.1), 1000 FP64 steps.
+
+    On L = 1 with dx = 1/64 the paper's mu = 5e-5 gives dt/tau = 2.4 at
+    CFL 0.01 (beyond the explicit Euler relaxation limit), so the workload
+    uses mu = 2e-3, well above the scheme's numerical viscosity at 64 cells.
+    """
+    wl = shear_wave(64, amp=1e-3, mach=0.1)
+    s, p = solver(wl, split=2, storage="f64", Pr=0.71, tau_ref=2e-3)
+    cfg = oracle_cfg(p)
+    f0, g0 = O.initial_state(wl.rho, wl.ux, wl.uy, wl.T, cfg)
+    sums0 = s.moments(fields=False)["sums"]
+    s.step(1000)
+    f, g = oracle_state(s)
+    fo, go = O.run(f0, g0, cfg, s.dt, 1000)
+    assert rel(f, fo) < 1e-12 and rel(g, go) < 1e-12
+    assert rel(f - f0, fo - f0) < 1e-8
+    sums = s.moments(fields=False)["sums"]
+    drift = np.abs(sums - sums0) / np.maximum(np.abs(sums0), 1.0)
+    assert drift.max() < 1e-12
+
+
+# ---------------------------------------------------------------- diagnostics and conservation
+def test_moment_fields_match_oracle():
+    wl = smooth_random(70, 37, seed=6)
+    s, p = solver(wl, split=2, storage="f64", tau_ref=0.02, cfl=0.1)
+    s.step(5)
+    m = s.moments()
+    f, g = oracle_state(s)
+    d = O.diagnostics(f, g, oracle_cfg(p))
+    for k in ("rho", "ux", "uy", "T"):
+        assert rel(m[k].cpu(), d[k]) < 1e-14, k
+    np.testing.assert_allclose(m["sums"], d["sums"].numpy(), rtol=1e-13)
+
+
+@pytest.mark.parametrize("split", (1, 2))
+@pytest.mark.parametrize("Pr", (0.5, 2.0))
+def test_periodic_conservation_fp64(split, Pr):
+    wl = smooth_random(96, 80, seed=7)
+    s, _ = solver(wl, split=split, storage="f64", Pr=Pr, tau_ref=0.02, cfl=0.1)
+    s0 = s.moments(fields=False)["sums"]
+    s.step(200)
+    s1 = s.moments(fields=False)["sums"]
+    drift = np.abs(s1 - s0) / np.abs(s0)
+    assert drift.max() < 1e-16 * 96 * 80 * 200 / 100, drift
+
+
+def test_uniform_state_fixed_point_all_storages():
+    wl = uniform(70, 12, rho=1.1, ux=0.3, uy=-0.1, T=1.05)
+    for storage in ("f64", "f32", "bf16_dev", "fp16_dev"):
+        s, _ = solver(wl, split=2, storage=storage, tau_ref=0.02, cfl=0.1)
+        X0 = s.store_populations()
+        s.step(10)
+        X1 = s.store_populations()
+        # 16-bit formats: the stored equilibrium is itself rounded, so relaxation may
+        # move it by at most the rounding of the deviation (~0.3 * 2^-8 or 2^-11)
+        tol = {"f64": 1e-15, "f32": 1e-6, "bf16_dev": 3e-3, "fp16_dev": 4e-4}[storage]
+        assert rel(X1, X0) < tol, storage
+
+
+# ---------------------------------------------------------------- 16-bit deviation storage
+@pytest.mark.parametrize("split", (1, 2))
+@pytest.mark.parametrize("storage,u", (("bf16_dev", 2.0 ** -8), ("fp16_dev", 2.0 ** -11)))
+def test_deviation_storage_step(split, storage, u):
+    wl = smooth_random(70, 20, seed=8, amp_T=0.05)
+    s, p = solver(wl, split=split, storage=storage, Pr=0.7, tau_ref=0.02, cfl=0.1)
+    cfg = oracle_cfg(p)
+    f0, g0 = oracle_state(s)  # decoded (already rounded) initial state
+    fo_ic, go_ic = O.initial_state(wl.rho, wl.ux, wl.uy, wl.T, cfg)
+    v, w = O.velocity_set(cfg)
+    wq = w.reshape(-1, 1, 1)
+    fref = wq * torch.ones_like(fo_ic)
+    s_g = s.store_populations().cpu()[1]
+    # rounding of the stored deviation bounds the initial error
+    assert float(((f0 - fo_ic).abs() / wq).max()) <= u * float(((fo_ic - fref).abs() / wq).max()) * 1.01 + 1e-7
+    s.step(1)
+    f1, g1 = oracle_state(s)
+    fo, go = O.step(f0, g0, cfg, s.dt)
+    dev_f = torch.linalg.vector_norm((fo - fref))
+    assert float(torch.linalg.vector_norm(f1 - fo)) <= 1.5 * u * float(dev_f) + 1e-6 * float(torch.linalg.vector_norm(fo))
+    assert torch.isfinite(s_g).all()
+
+
+def test_load_store_roundtrip():
+    wl = smooth_random(66, 10, seed=9)
+    for storage in ("f64", "f32"):
+        s, p = solver(wl, split=2, storage=storage, tau_ref=0.02)
+        X = s.store_populations()
+        Y = X * (1 + 1e-3 * torch.sin(torch.arange(X.numel(), device=DEV, dtype=torch.float64)).reshape(X.shape))
+        s.load_populations(Y)
+        Z = s.store_populations()
+        assert rel(Z, Y) < (1e-16 if storage == "f64" else 1e-7)
+
+
+# ---------------------------------------------------------------- full-size workloads, sampled cells
+def sampled_check(s: Solver, p, nsamples=96, seed=0):
+    """Run one GPU step and compare sampled cells with the oracle's update of the same state."""
+    cfg = oracle_cfg(p)
+    rng = np.random.default_rng(seed)
+    ys = torch.tensor(np.concatenate([rng.integers(0, p.ny, nsamples - 4), [0, p.ny - 1, 0, p.ny - 1]]))
+    xs = torch.tensor(np.concatenate([rng.integers(0, p.nx, nsamples - 4), [0, p.nx - 1, p.nx - 1, 0]]))
+    yi, xi = O.window_indices(cfg, ys, xs)
+    X = s.store_populations()
+    win = X[:, :, yi.to(DEV)[:, :, None], xi.to(DEV)[:, None, :]].cpu()  # [2, Q, S, 5, 5]
+    del X
+    s.step(1)
+    X1 = s.store_populations()
+    got = X1[:, :, ys.to(DEV), xs.to(DEV)].cpu()
+    del X1
+    fo, go = O.window_step(win[0], win[1], cfg, s.dt)
+    return got, torch.stack([fo, go]), win[:, :, :, 2, 2]
+
+
+@pytest.mark.parametrize("storage,tol", (("f32", 1e-5), ("f64", 1e-12)))
+def test_vortex_1024_sampled(storage, tol):
+    wl = isentropic_vortex(1024, seed=0, mach_adv=1.0, mach_v=0.3, r_frac=0.05)
+    s, p = solver(wl, split=2, storage=storage, Pr=0.71, tau_ref=5e-5)
+    s.step(2)
+    got, ref, before = sampled_check(s, p)
+    assert rel(got, ref) < tol
+    if storage == "f64":
+        assert rel(got - before, ref - before) < 1e-9
+
+
+@pytest.mark.parametrize("Pr,gamma", ((0.1, 1.4), (2.0, 5.0 / 3.0)))
+def test_shock_vortex_2048x1024_sampled(Pr, gamma):
+    wl = shock_vortex(2048, 1024, mach_s=1.2, mach_v=0.25, r_frac=0.075, gamma=gamma)
+    s, p = solver(wl, split=2, storage="f32", Pr=Pr, gamma=gamma, tau_ref=wl.phys["mu"], bc_x="zero_gradient",
+                  bc_y="periodic")
+    s.step(2)
+    got, ref, _ = sampled_check(s, p)
+    assert rel(got, ref) < 1e-5
+
+
+@pytest.mark.parametrize("storage,tol", (("f32", 1e-5), ("f64", 1e-12)))
+def test_thermal_wave_4096_sampled(storage, tol):
+    wl = thermal_wave(4096, seed=0)
+    s, p = solver(wl, split=2, storage=storage, Pr=0.5, tau_ref=5e-5)
+    s.step(1)
+    got, ref, _ = sampled_check(s, p, nsamples=64)
+    assert rel(got, ref) < tol
+
+
+# ---------------------------------------------------------------- errors raised from device checks
+def test_nonphysical_initial_state_rejected():
+    wl = smooth_random(16, 16, seed=1)
+    wl.T[3, 4] = -1.0
+    with pytest.raises(DVBMError) as e:
+        solver(wl, tau_ref=0.02)
+    assert e.value.code == dvbm.DVBM_ENAN
+
+
+def test_stiff_relaxation_rejected():
+    wl = smooth_random(16, 16, seed=1)
+    with pytest.raises(DVBMError) as e:
+        solver(wl, tau_ref=1e-6, cfl=0.5)
+    assert e.value.code == dvbm.DVBM_ESTIFF
