@@ -5,7 +5,7 @@
 //                     (quasi-)equilibria, two-time relaxation and NND flux
 //                     divergence of every population, fused; one thread per
 //                     cell, populations read once from HBM as coalesced
-//                     structure-of-arrays rows, stencil neighbours through L1/L2.
+//                     structure-of-arrays rows, flux stencils from LDS tiles.
 //   k_init            equilibrium populations of macroscopic fields (Sec. III A 3).
 //   k_moments         rho, u, T fields and per-block float64 conservation sums.
 //   k_speed           per-block extrema of the initial fields (time step, checks).
@@ -25,19 +25,39 @@
 
 namespace dvbm {
 
-constexpr int TX = 64;  // cells per wavefront row (x)
-constexpr int TY = 4;   // wavefront rows per workgroup (y)
+// Two step kernels, chosen per storage format by measurement on MI355X:
+//  - per-cell (register) kernel: a cell's 2Q populations live in registers,
+//    flux stencils come through the vector L1/L2 (float32 and 16-bit
+//    storage);
+//  - LDS-tiled kernel: groups of N1 population planes are staged with their
+//    ghost layers in LDS (float64 storage, whose larger rows make the cache
+//    path the bottleneck).
 constexpr int RED_BLOCKS = 1024;
 constexpr int RED_THREADS = 256;
+constexpr int CELL_TX = 64, CELL_TY = 4;  // per-cell kernel: 64 x 4 cells per workgroup
+constexpr int TILE_TX = 64, TILE_TY = 4;  // LDS kernel tile
+
+template <class S>
+struct UseTiles {
+  static constexpr bool value = sizeof(typename S::T) == 8;
+};
 
 // ------------------------------------------------------------ fused step
 template <int SPLIT, class S, int BCX, int BCY, int PRM>
-__global__ __launch_bounds__(TX* TY) void k_collide_advect(const typename S::T* __restrict__ src,
-                                                           typename S::T* __restrict__ dst, KParams kp) {
-  const int x = blockIdx.x * TX + threadIdx.x;
-  const int y = blockIdx.y * TY + threadIdx.y;
+__global__ __launch_bounds__(CELL_TX* CELL_TY) void k_collide_advect(const typename S::T* __restrict__ src,
+                                                                     typename S::T* __restrict__ dst, KParams kp) {
+  const int x = blockIdx.x * CELL_TX + threadIdx.x;
+  const int y = blockIdx.y * CELL_TY + threadIdx.y;
   if (x >= kp.nx || y >= kp.ny) return;
   cell_update<SPLIT, S, BCX, BCY, PRM>(src, dst, kp, x, y);
+}
+
+template <int SPLIT, class S, int BCX, int BCY, int PRM>
+__global__ __launch_bounds__(TILE_TX* TILE_TY) void k_collide_advect_lds(const typename S::T* __restrict__ src,
+                                                                         typename S::T* __restrict__ dst,
+                                                                         KParams kp) {
+  __shared__ PlaneTile<typename S::C, TILE_TX, TILE_TY, Set<SPLIT>::N1> lds;
+  tile_update<SPLIT, S, BCX, BCY, PRM, TILE_TX, TILE_TY>(src, dst, kp, blockIdx.x, blockIdx.y, lds);
 }
 
 // ------------------------------------------------------------ equilibrium initialisation
@@ -260,6 +280,9 @@ std::string check_params(const dvbm_params* p) {
   if (!std::isfinite(p->dt)) return "dt must be finite";
   const double nmax = 2147483647.0;
   if (double(p->nx) * double(p->ny) > nmax) return "nx * ny too large";
+  const double pitch = double((int64_t(p->nx) + 63) / 64 * 64);
+  if (pitch * double(p->ny) * storage_bytes(p->storage) * (p->split == 1 ? 16 : 25) > 4294967295.0)
+    return "one distribution (Q * ny * pitch elements) must be smaller than 4 GiB";
   return "";
 }
 
@@ -307,20 +330,31 @@ KParams make_kparams(const dvbm_params& p, double dt) {
   return k;
 }
 
-template <int SPLIT, class S, int BCX, int BCY>
-void launch_step_bc(const dvbm_handle* h, const void* src, void* dst) {
+template <int SPLIT, class S, int BCX, int BCY, int PRM>
+void launch_step_pr(const dvbm_handle* h, const void* src, void* dst) {
   using T = typename S::T;
-  const dim3 block(TX, TY);
-  const dim3 grid((h->p.nx + TX - 1) / TX, (h->p.ny + TY - 1) / TY);
-  const int prm = pr_mode(h->p.Pr);
   const T* s = static_cast<const T*>(src);
   T* d = static_cast<T*>(dst);
+  if constexpr (UseTiles<S>::value) {
+    const dim3 grid((h->p.nx + TILE_TX - 1) / TILE_TX, (h->p.ny + TILE_TY - 1) / TILE_TY);
+    hipLaunchKernelGGL((k_collide_advect_lds<SPLIT, S, BCX, BCY, PRM>), grid, dim3(TILE_TX, TILE_TY), 0, h->stream,
+                       s, d, h->kp);
+  } else {
+    const dim3 grid((h->p.nx + CELL_TX - 1) / CELL_TX, (h->p.ny + CELL_TY - 1) / CELL_TY);
+    hipLaunchKernelGGL((k_collide_advect<SPLIT, S, BCX, BCY, PRM>), grid, dim3(CELL_TX, CELL_TY), 0, h->stream, s,
+                       d, h->kp);
+  }
+}
+
+template <int SPLIT, class S, int BCX, int BCY>
+void launch_step_bc(const dvbm_handle* h, const void* src, void* dst) {
+  const int prm = pr_mode(h->p.Pr);
   if (prm == PR_UNIT)
-    hipLaunchKernelGGL((k_collide_advect<SPLIT, S, BCX, BCY, PR_UNIT>), grid, block, 0, h->stream, s, d, h->kp);
+    launch_step_pr<SPLIT, S, BCX, BCY, PR_UNIT>(h, src, dst);
   else if (prm == PR_LOW)
-    hipLaunchKernelGGL((k_collide_advect<SPLIT, S, BCX, BCY, PR_LOW>), grid, block, 0, h->stream, s, d, h->kp);
+    launch_step_pr<SPLIT, S, BCX, BCY, PR_LOW>(h, src, dst);
   else
-    hipLaunchKernelGGL((k_collide_advect<SPLIT, S, BCX, BCY, PR_HIGH>), grid, block, 0, h->stream, s, d, h->kp);
+    launch_step_pr<SPLIT, S, BCX, BCY, PR_HIGH>(h, src, dst);
 }
 
 template <int SPLIT, class S>

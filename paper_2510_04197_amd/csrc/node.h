@@ -85,26 +85,28 @@ struct StoreF16 {
 __device__ inline double med3(double a, double b, double c) { return fmax(fmin(a, b), fmin(fmax(a, b), c)); }
 __device__ inline float med3(float a, float b, float c) { return __builtin_amdgcn_fmed3f(a, b, c); }
 
-// (b/2) phi(a, b) of the generalised van Leer limiter (Sec. III A 2) in the
-// division-free form  1/2 minmod(beta a, (a + b)/2, beta b);  beta2 = 2 beta.
+// 4 (b/2) phi(a, b) of the generalised van Leer limiter (Sec. III A 2) in the
+// division-free form  2 minmod(beta a, (a + b)/2, beta b);  beta2 = 2 beta.
 template <class R>
-__device__ inline R lim(R a, R b, R beta2) {
-  return R(0.25) * med3(med3(beta2 * a, beta2 * b, R(0)), a + b, R(0));
+__device__ inline R lim4(R a, R b, R beta2) {
+  return med3(med3(beta2 * a, beta2 * b, R(0)), a + b, R(0));
 }
 
 // X_{c+1/2} - X_{c-1/2} of the NND reconstruction for a positive velocity
-// component; m2, m1, c0, p1 are the values at c-2 .. c+1.
+// component; m2, m1, c0, p1 are the values at c-2 .. c+1:
+//   (c0 + L(d1, d2)) - (m1 + L(d0, d1)) = d1 + (L(d1, d2) - L(d0, d1)).
 template <class R>
 __device__ inline R dface_pos(R m2, R m1, R c0, R p1, R beta2) {
   const R d0 = m1 - m2, d1 = c0 - m1, d2 = p1 - c0;
-  return d1 + (lim(d1, d2, beta2) - lim(d0, d1, beta2));
+  return d1 + R(0.25) * (lim4(d1, d2, beta2) - lim4(d0, d1, beta2));
 }
 
-// The same for a negative velocity component; m1, c0, p1, p2 at c-1 .. c+2.
+// The same for a negative velocity component; m1, c0, p1, p2 at c-1 .. c+2:
+//   (p1 + L(p1 - p2, c0 - p1)) - (c0 + L(c0 - p1, m1 - c0)).
 template <class R>
 __device__ inline R dface_neg(R m1, R c0, R p1, R p2, R beta2) {
   const R e0 = c0 - p1, e1 = p1 - p2, em = m1 - c0;
-  return (lim(e1, e0, beta2) - lim(e0, em, beta2)) - e0;
+  return R(0.25) * (lim4(e1, e0, beta2) - lim4(e0, em, beta2)) - e0;
 }
 
 // Sums over the 1-D nodes of v, xi v, xi^2 v, xi^3 v, folding +-xi pairs.

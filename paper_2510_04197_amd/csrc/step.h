@@ -3,6 +3,8 @@
 // divergence, encode.
 #pragma once
 
+#include <utility>
+
 #include "node.h"
 
 namespace dvbm {
@@ -32,6 +34,67 @@ __device__ inline int wrap(int j, int n) {
 // One time step of Eq. (finalDiscretePDE) for the cell (x, y): reads the
 // populations of the cell and its flux stencil from src, writes the cell's
 // new populations to dst.
+// Each distribution (Q planes) is addressed through one buffer resource
+// (wave-uniform, < 4 GiB), a scalar per-plane offset and a 32-bit per-lane
+// byte offset, so the address arithmetic stays out of the vector ALU.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int RSRC_WORD3 = 0x00020000;  // 32-bit data format, raw (untyped) access
+
+__device__ inline rsrc_t dist_rsrc(const void* base, int d, uint32_t dist_bytes) {
+  const char* p = static_cast<const char*>(base) + size_t(d) * size_t(dist_bytes);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(p), 0, dist_bytes, RSRC_WORD3);
+}
+
+template <class T>
+struct Buf;
+template <>
+struct Buf<float> {
+  __device__ static float ld(rsrc_t r, uint32_t so, uint32_t o) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o, so, 0));
+  }
+  __device__ static void st(rsrc_t r, uint32_t so, uint32_t o, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, o, so, 0);
+  }
+};
+template <>
+struct Buf<double> {
+  __device__ static double ld(rsrc_t r, uint32_t so, uint32_t o) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, o, so, 0));
+  }
+  __device__ static void st(rsrc_t r, uint32_t so, uint32_t o, double v) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, o, so, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, o, so, 0);
+  }
+};
+template <>
+struct Buf<uint16_t> {
+  __device__ static uint16_t ld(rsrc_t r, uint32_t so, uint32_t o) { return __builtin_amdgcn_raw_buffer_load_b16(r, o, so, 0); }
+  __device__ static void st(rsrc_t r, uint32_t so, uint32_t o, uint16_t v) { __builtin_amdgcn_raw_buffer_store_b16(v, r, o, so, 0); }
+};
+template <>
+struct Buf<_Float16> {
+  __device__ static _Float16 ld(rsrc_t r, uint32_t so, uint32_t o) {
+    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, o, so, 0));
+  }
+  __device__ static void st(rsrc_t r, uint32_t so, uint32_t o, _Float16 v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, o, so, 0);
+  }
+};
+
+// Compile-time loop: f(std::integral_constant<int, k>) for k = 0 .. N-1.
+template <class F, int... K>
+__device__ inline void static_for_impl(F&& f, std::integer_sequence<int, K...>) {
+  (f(std::integral_constant<int, K>{}), ...);
+}
+template <int N, class F>
+__device__ inline void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// One time step of Eq. (finalDiscretePDE) for the cell (x, y), one thread
+// per cell: the cell's 2Q populations stay in registers (moments, then the
+// collision of each population), the flux stencil of every population is
+// read through the vector L1/L2 caches.
 template <int SPLIT, class S, int BCX, int BCY, int PRM>
 __device__ inline void cell_update(const typename S::T* __restrict__ src, typename S::T* __restrict__ dst,
                                    const KParams& kp, int x, int y) {
@@ -39,36 +102,43 @@ __device__ inline void cell_update(const typename S::T* __restrict__ src, typena
   using T = typename S::T;
   constexpr int N1 = Set<SPLIT>::N1;
   constexpr int Q = Set<SPLIT>::Q;
+  constexpr uint32_t SZ = sizeof(T);
   using L = GH<N1>;
 
-  const int xm2 = wrap<BCX>(x - 2, kp.nx), xm1 = wrap<BCX>(x - 1, kp.nx);
-  const int xp1 = wrap<BCX>(x + 1, kp.nx), xp2 = wrap<BCX>(x + 2, kp.nx);
-  const int64_t r0 = int64_t(y) * kp.pitch;
-  const int64_t rm2 = int64_t(wrap<BCY>(y - 2, kp.ny)) * kp.pitch;
-  const int64_t rm1 = int64_t(wrap<BCY>(y - 1, kp.ny)) * kp.pitch;
-  const int64_t rp1 = int64_t(wrap<BCY>(y + 1, kp.ny)) * kp.pitch;
-  const int64_t rp2 = int64_t(wrap<BCY>(y + 2, kp.ny)) * kp.pitch;
+  const uint32_t pitch = uint32_t(kp.pitch);
+  const uint32_t row0 = uint32_t(y) * pitch;
+  const uint32_t o0 = (row0 + uint32_t(x)) * SZ;
+  const uint32_t oxm2 = (row0 + uint32_t(wrap<BCX>(x - 2, kp.nx))) * SZ;
+  const uint32_t oxm1 = (row0 + uint32_t(wrap<BCX>(x - 1, kp.nx))) * SZ;
+  const uint32_t oxp1 = (row0 + uint32_t(wrap<BCX>(x + 1, kp.nx))) * SZ;
+  const uint32_t oxp2 = (row0 + uint32_t(wrap<BCX>(x + 2, kp.nx))) * SZ;
+  const uint32_t oym2 = (uint32_t(wrap<BCY>(y - 2, kp.ny)) * pitch + uint32_t(x)) * SZ;
+  const uint32_t oym1 = (uint32_t(wrap<BCY>(y - 1, kp.ny)) * pitch + uint32_t(x)) * SZ;
+  const uint32_t oyp1 = (uint32_t(wrap<BCY>(y + 1, kp.ny)) * pitch + uint32_t(x)) * SZ;
+  const uint32_t oyp2 = (uint32_t(wrap<BCY>(y + 2, kp.ny)) * pitch + uint32_t(x)) * SZ;
+  const uint32_t plane_bytes = uint32_t(kp.plane) * SZ;
+  const uint32_t dist_bytes = plane_bytes * uint32_t(Q);
+  const rsrc_t rsrc_src[2] = {dist_rsrc(src, 0, dist_bytes), dist_rsrc(src, 1, dist_bytes)};
+  const rsrc_t rsrc_dst[2] = {dist_rsrc(dst, 0, dist_bytes), dist_rsrc(dst, 1, dist_bytes)};
 
-  R xf[Q], xg[Q];  // stored values (deviation units for the 16-bit formats)
+  R xs[2][Q];  // stored values (deviation units for the 16-bit formats)
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    xf[i] = S::raw(src[int64_t(i) * kp.plane + r0 + x]);
-    xg[i] = S::raw(src[int64_t(Q + i) * kp.plane + r0 + x]);
-  }
-  R f[Q], g[Q];  // decoded populations
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) xs[d][i] = S::raw(Buf<T>::ld(rsrc_src[d], i * plane_bytes, o0));
+  R X[2][Q];  // decoded populations
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (S::dev) {
       const double w = weight<SPLIT>(i);
-      f[i] = R(w) * (R(1) + xf[i]);
-      g[i] = R(w) * (R(g_ref_over_w<SPLIT>(kp, i)) + xg[i]);
+      X[0][i] = R(w) * (R(1) + xs[0][i]);
+      X[1][i] = R(w) * (R(g_ref_over_w<SPLIT>(kp, i)) + xs[1][i]);
     } else {
-      f[i] = xf[i];
-      g[i] = xg[i];
+      X[0][i] = xs[0][i];
+      X[1][i] = xs[1][i];
     }
   }
-
-  const NodeMoments m = node_moments<N1>(f, g);
+  const NodeMoments m = node_moments<N1>(X[0], X[1]);
   R bf[5][5], bg[3][3], om1;
   collision_coeffs<SPLIT, PRM, R>(m, kp, bf, bg, om1);
 
@@ -76,38 +146,242 @@ __device__ inline void cell_update(const typename S::T* __restrict__ src, typena
   const R keep = R(1) - om1;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    f[i] *= keep;
-    g[i] *= keep;
+    X[0][i] *= keep;
+    X[1][i] *= keep;
   }
-  expand_add<N1, Set<SPLIT>::NF>(bf, f);
-  expand_add<N1, 2>(bg, g);
+  expand_add<N1, Set<SPLIT>::NF>(bf, X[0]);
+  expand_add<N1, 2>(bg, X[1]);
 
   // advection: -(dt/dx) v_x (X_{x+1/2} - X_{x-1/2}) - (dt/dy) v_y (X_{y+1/2} - X_{y-1/2})
   const R beta2 = R(kp.beta2);
+  const R kx = R(kp.kx), ky = R(kp.ky);
 #pragma unroll
   for (int d = 0; d < 2; ++d) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const double xa = L::xi(i / N1), xb = L::xi(i % N1);
-      const T* pl = src + int64_t(d * Q + i) * kp.plane;
-      const R c0 = d == 0 ? xf[i] : xg[i];
+      const rsrc_t pl = rsrc_src[d];
+      const uint32_t so = i * plane_bytes;
+      const R c0 = xs[d][i];
       R div = R(0);
-      if (xa > 0.0) {
-        div += R(kp.kx * xa) * dface_pos(S::raw(pl[r0 + xm2]), S::raw(pl[r0 + xm1]), c0, S::raw(pl[r0 + xp1]), beta2);
-      } else if (xa < 0.0) {
-        div += R(kp.kx * xa) * dface_neg(S::raw(pl[r0 + xm1]), c0, S::raw(pl[r0 + xp1]), S::raw(pl[r0 + xp2]), beta2);
-      }
-      if (xb > 0.0) {
-        div += R(kp.ky * xb) * dface_pos(S::raw(pl[rm2 + x]), S::raw(pl[rm1 + x]), c0, S::raw(pl[rp1 + x]), beta2);
-      } else if (xb < 0.0) {
-        div += R(kp.ky * xb) * dface_neg(S::raw(pl[rm1 + x]), c0, S::raw(pl[rp1 + x]), S::raw(pl[rp2 + x]), beta2);
-      }
+      if (xa > 0.0)
+        div += kx * R(xa) * dface_pos(S::raw(Buf<T>::ld(pl, so, oxm2)), S::raw(Buf<T>::ld(pl, so, oxm1)), c0,
+                                        S::raw(Buf<T>::ld(pl, so, oxp1)), beta2);
+      else if (xa < 0.0)
+        div += kx * R(xa) * dface_neg(S::raw(Buf<T>::ld(pl, so, oxm1)), c0, S::raw(Buf<T>::ld(pl, so, oxp1)),
+                                        S::raw(Buf<T>::ld(pl, so, oxp2)), beta2);
+      if (xb > 0.0)
+        div += ky * R(xb) * dface_pos(S::raw(Buf<T>::ld(pl, so, oym2)), S::raw(Buf<T>::ld(pl, so, oym1)), c0,
+                                        S::raw(Buf<T>::ld(pl, so, oyp1)), beta2);
+      else if (xb < 0.0)
+        div += ky * R(xb) * dface_neg(S::raw(Buf<T>::ld(pl, so, oym1)), c0, S::raw(Buf<T>::ld(pl, so, oyp1)),
+                                        S::raw(Buf<T>::ld(pl, so, oyp2)), beta2);
       const double w = weight<SPLIT>(i);
       const R rr = S::dev ? R(d == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i)) : R(0);
-      const R xnew = (d == 0 ? f[i] : g[i]) - (S::dev ? R(w) * div : div);
-      dst[int64_t(d * Q + i) * kp.plane + r0 + x] = S::enc(xnew, R(1.0 / w), rr);
+      const R xnew = X[d][i] - (S::dev ? R(w) * div : div);
+      Buf<T>::st(rsrc_dst[d], so, o0, S::enc(xnew, R(1.0 / w), rr));
     }
   }
+}
+
+// Neighbour index under the boundary rule, for any integer j.
+template <int BC>
+__device__ inline int wrap_any(int j, int n) {
+  if (BC == BC_PERIODIC) {
+    const int r = j % n;
+    return r < 0 ? r + n : r;
+  }
+  return j < 0 ? 0 : (j >= n ? n - 1 : j);
+}
+
+// Halo slot s of a (TX + 4) x (TY + 4) tile region (two ghost layers on
+// every side): rows 0-1 full, then the two left / two right columns of the
+// TY interior rows, then rows TY+2, TY+3 full.
+template <int TX, int TY>
+__device__ inline void halo_slot(int s, int& hy, int& hx) {
+  constexpr int W = TX + 4;
+  if (s < 2 * W) {
+    hy = s / W;
+    hx = s % W;
+    return;
+  }
+  s -= 2 * W;
+  if (s < 4 * TY) {
+    const int c = s % 4;
+    hy = 2 + s / 4;
+    hx = c < 2 ? c : TX + c;
+    return;
+  }
+  s -= 4 * TY;
+  hy = TY + 2 + s / W;
+  hx = s % W;
+}
+
+// LDS staging area: G population planes, each the tile plus two ghost
+// layers, double-buffered so that one barrier per group of G suffices.
+template <class R, int TX, int TY, int G>
+struct PlaneTile {
+  R v[2][G][TY + 4][TX + 4];
+};
+
+// One time step of Eq. (finalDiscretePDE) for the TX x TY cells of tile
+// (bx, by), one thread per cell.  Pass 1 reads the cell's 2Q populations
+// (coalesced rows) and builds the relaxation coefficients from float64
+// moments.  Pass 2 walks the populations: each plane's tile and ghost layers
+// are staged in LDS (own value from registers, ghosts from global memory),
+// and every thread reads its flux stencil from LDS.  Threads of a partial
+// tile hold the values of their wrapped / clamped cells so that every staged
+// entry is the one the stencil needs; they store nothing.
+template <int SPLIT, class S, int BCX, int BCY, int PRM, int TX, int TY>
+__device__ inline void tile_update(const typename S::T* __restrict__ src, typename S::T* __restrict__ dst,
+                                   const KParams& kp, int bx, int by,
+                                   PlaneTile<typename S::C, TX, TY, Set<SPLIT>::N1>& lds) {
+  using R = typename S::C;
+  using T = typename S::T;
+  constexpr int N1 = Set<SPLIT>::N1;
+  constexpr int Q = Set<SPLIT>::Q;
+  constexpr int NF = Set<SPLIT>::NF;
+  constexpr uint32_t SZ = sizeof(T);
+  constexpr int NT = TX * TY;
+  constexpr int NH = (TX + 4) * (TY + 4) - TX * TY;
+  constexpr int H = (NH + NT - 1) / NT;
+  using L = GH<N1>;
+
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+  const int x = bx * TX + tx, y = by * TY + ty;
+  const bool valid = x < kp.nx && y < kp.ny;
+  const uint32_t pitch = uint32_t(kp.pitch);
+  const uint32_t o0 =
+      (uint32_t(wrap_any<BCY>(y, kp.ny)) * pitch + uint32_t(wrap_any<BCX>(x, kp.nx))) * SZ;
+  uint32_t hoff[H];
+  int hidx[H];
+  bool hval[H];
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const int s = tid + j * NT;
+    hval[j] = s < NH;
+    int hy = 0, hx = 0;
+    if (hval[j]) halo_slot<TX, TY>(s, hy, hx);
+    const int gx = wrap_any<BCX>(bx * TX + hx - 2, kp.nx);
+    const int gy = wrap_any<BCY>(by * TY + hy - 2, kp.ny);
+    hoff[j] = (uint32_t(gy) * pitch + uint32_t(gx)) * SZ;
+    hidx[j] = hy * (TX + 4) + hx;
+  }
+  const uint32_t plane_bytes = uint32_t(kp.plane) * SZ;
+  const uint32_t dist_bytes = plane_bytes * uint32_t(Q);
+  const rsrc_t rsrc_src[2] = {dist_rsrc(src, 0, dist_bytes), dist_rsrc(src, 1, dist_bytes)};
+  const rsrc_t rsrc_dst[2] = {dist_rsrc(dst, 0, dist_bytes), dist_rsrc(dst, 1, dist_bytes)};
+
+  // Pass 1: the cell's populations and their float64 moments.
+  NodeMoments m;
+  {
+    R f[Q], g[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const R rf = S::raw(Buf<T>::ld(rsrc_src[0], i * plane_bytes, o0));
+      const R rg = S::raw(Buf<T>::ld(rsrc_src[1], i * plane_bytes, o0));
+      if (S::dev) {
+        const double w = weight<SPLIT>(i);
+        f[i] = R(w) * (R(1) + rf);
+        g[i] = R(w) * (R(g_ref_over_w<SPLIT>(kp, i)) + rg);
+      } else {
+        f[i] = rf;
+        g[i] = rg;
+      }
+    }
+    m = node_moments<N1>(f, g);
+  }
+  R bf[5][5], bg[3][3], om1;
+  collision_coeffs<SPLIT, PRM, R>(m, kp, bf, bg, om1);
+  const R keep = R(1) - om1;
+  const R beta2 = R(kp.beta2);
+  const R kx = R(kp.kx), ky = R(kp.ky);
+  // Pass 2 re-reads each population (a cache hit) rather than pinning all 2Q
+  // of them in registers.
+  __asm__ volatile("" ::: "memory");
+
+  // Pass 2: groups gk = d N1 + b of the N1 populations i = a N1 + b that share
+  // the y-node b (so the Grad expansion factors into
+  // sum_p w_a He_p(xi_a)/p! c_p(b)).  A group's planes are staged in LDS with
+  // one barrier; the loads of group gk + 1 are issued before that barrier.
+  constexpr int W = TX + 4;
+  constexpr int PL = (TY + 4) * W;
+  constexpr int NMAX = 4;
+  const int me = (ty + 2) * W + tx + 2;
+  R cur[N1], curh[N1][H];
+  auto fetch = [&](int gk, R (&c)[N1], R (&h)[N1][H]) {
+    const int d = gk / N1, yb = gk % N1;
+#pragma unroll
+    for (int xa = 0; xa < N1; ++xa) {
+      const uint32_t so = (xa * N1 + yb) * plane_bytes;
+      c[xa] = S::raw(Buf<T>::ld(rsrc_src[d], so, o0));
+#pragma unroll
+      for (int j = 0; j < H; ++j) h[xa][j] = hval[j] ? S::raw(Buf<T>::ld(rsrc_src[d], so, hoff[j])) : R(0);
+    }
+  };
+  fetch(0, cur, curh);
+  static_for<2 * N1>([&](auto gc) {
+    constexpr int gk = decltype(gc)::value;
+    constexpr int d = gk / N1, yb = gk % N1;
+    constexpr int N = d == 0 ? NF : 2;
+    constexpr double xb = L::xi(yb);
+    R c[NMAX + 1];
+#pragma unroll
+    for (int p = 0; p <= NMAX; ++p) {
+      c[p] = R(0);
+      if (p > N) continue;
+#pragma unroll
+      for (int q = 0; p + q <= N; ++q) {
+        const double h = hn(q, xb);
+        if (h != 0.0) c[p] += (d == 0 ? bf[p][q] : bg[p][q]) * R(h);
+      }
+    }
+    R c0s[N1];
+#pragma unroll
+    for (int xa = 0; xa < N1; ++xa) {
+      R* buf = &lds.v[gk & 1][xa][0][0];
+      c0s[xa] = cur[xa];
+      buf[me] = cur[xa];
+#pragma unroll
+      for (int j = 0; j < H; ++j)
+        if (hval[j]) buf[hidx[j]] = curh[xa][j];
+    }
+    if (gk + 1 < 2 * N1) fetch(gk + 1, cur, curh);
+    __syncthreads();
+
+    static_for<N1>([&](auto ac) {
+      constexpr int xa = decltype(ac)::value;
+      constexpr int i = xa * N1 + yb;
+      constexpr double xv = L::xi(xa);
+      constexpr double w = GH<N1>::w(xa) * GH<N1>::w(yb);
+      const R* buf = &lds.v[gk & 1][xa][0][0];
+      const R c0 = c0s[xa];
+      const uint32_t so = i * plane_bytes;
+      const R rr = S::dev ? R(d == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i)) : R(0);
+      const R X = S::dev ? R(w) * (rr + c0) : c0;
+      // collision: (1 - om1) X + w_i sum_p He_p(xi_a)/p! c_p
+      R xn = keep * X;
+#pragma unroll
+      for (int p = 0; p <= NMAX; ++p) {
+        if (p > N) continue;
+        const double h = hn(p, xv);
+        if (h != 0.0) xn += R(w * h) * c[p];
+      }
+      // advection: -(dt/dx) v_x (X_{x+1/2} - X_{x-1/2}) - (dt/dy) v_y (X_{y+1/2} - X_{y-1/2})
+      R div = R(0);
+      if (xv > 0.0)
+        div += kx * R(xv) * dface_pos(buf[me - 2], buf[me - 1], c0, buf[me + 1], beta2);
+      else if (xv < 0.0)
+        div += kx * R(xv) * dface_neg(buf[me - 1], c0, buf[me + 1], buf[me + 2], beta2);
+      if (xb > 0.0)
+        div += ky * R(xb) * dface_pos(buf[me - 2 * W], buf[me - W], c0, buf[me + W], beta2);
+      else if (xb < 0.0)
+        div += ky * R(xb) * dface_neg(buf[me - W], c0, buf[me + W], buf[me + 2 * W], beta2);
+      xn -= S::dev ? R(w) * div : div;
+      if (valid) Buf<T>::st(rsrc_dst[d], so, o0, S::enc(xn, R(1.0 / w), rr));
+    });
+  });
+  (void)PL;
 }
 
 }  // namespace dvbm
