@@ -162,6 +162,39 @@ int dvbm_state_index(const dvbm_handle* h);
  * a checkpoint into it. */
 int dvbm_set_state_index(dvbm_handle* h, int index);
 
+/*
+ * Discrete adjoint (reverse-mode derivative of the update above; it is not
+ * part of the paper and follows the discretise-then-differentiate rule: the
+ * limiter is differentiated on the branch the forward step takes, and dt is
+ * held fixed).  Supported for DVBM_F64 and DVBM_F32 storage (EINVAL
+ * otherwise); the arithmetic is float64.  Cotangents lam are dense device
+ * float64 arrays lam[2][Q][ny][nx] of dvbm_adjoint_bytes() bytes.
+ */
+size_t dvbm_adjoint_bytes(const dvbm_params* p);
+
+/* lam_n = (dX_{n+1}/dX_n)^T lam_np1 for the step that maps state_n (a device
+ * buffer in the population layout above, e.g. a checkpoint copy) to
+ * X_{n+1}.  When dparams != NULL (device double[2]) it is incremented by
+ * (dX_{n+1}/dtau_ref)^T lam_np1 and (dX_{n+1}/dPr)^T lam_np1 (at Pr == 1,
+ * where Table I has no quasi-equilibrium, the Pr entry is 0).  lam_np1 and
+ * lam_n must not overlap.  Asynchronous. */
+int dvbm_adjoint_step(dvbm_handle* h, const void* state_n, const double* lam_np1, double* lam_n,
+                      double* dparams);
+
+/* lam = sum of (d field / dX)^T d_field over the macroscopic fields of state
+ * (rho, u_x, u_y, T of Eqs. eq_quadratur1-3); any d_* may be NULL (zero).
+ * d_* are device float64 arrays of ny*nx.  Asynchronous. */
+int dvbm_adjoint_moments(dvbm_handle* h, const void* state, const double* d_rho, const double* d_ux,
+                         const double* d_uy, const double* d_T, double* lam);
+
+/* Cotangents of the initial fields through the equilibrium initialisation:
+ * d_field = (dX_0/d field)^T lam0 for the device float64 fields rho, ux, uy,
+ * T (the values given to dvbm_init); outputs that are NULL are skipped.
+ * Asynchronous. */
+int dvbm_adjoint_init(dvbm_handle* h, const double* lam0, const double* rho, const double* ux,
+                      const double* uy, const double* T, double* d_rho, double* d_ux, double* d_uy,
+                      double* d_T);
+
 /* Release the handle (host memory only).  NULL is ignored. */
 void dvbm_destroy(dvbm_handle* h);
 

@@ -16,3 +16,4 @@ from .dvbm import (  # noqa: F401
     num_populations,
     velocity_set,
 )
+from .autograd import rollout_temperature  # noqa: F401

@@ -22,6 +22,7 @@
 #include "lattice.h"
 #include "node.h"
 #include "step.h"
+#include "adjoint.h"
 
 namespace dvbm {
 
@@ -234,6 +235,77 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(const double* __restrict
   block_reduce4(v, mode, out);
 }
 
+// ------------------------------------------------------------ adjoint
+template <int SPLIT, class S, int BCX, int BCY, int PRM>
+__global__ __launch_bounds__(RED_THREADS) void k_adjoint_step(const typename S::T* __restrict__ state,
+                                                              const double* __restrict__ lam1,
+                                                              double* __restrict__ lam0, KParams kp, double tau_ref,
+                                                              double* partials) {
+  const int64_t n = int64_t(kp.nx) * kp.ny;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < n; c += int64_t(gridDim.x) * blockDim.x) {
+    const int y = int(c / kp.nx), x = int(c % kp.nx);
+    cell_adjoint<SPLIT, S, BCX, BCY, PRM>(state, lam1, lam0, kp, x, y, tau_ref, acc[0], acc[1]);
+  }
+  const int mode[4] = {0, 0, 0, 0};
+  block_reduce4(acc, mode, partials + 4 * blockIdx.x);
+}
+
+__global__ void k_accumulate2(const double* __restrict__ sums, double* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    out[0] += sums[0];
+    out[1] += sums[1];
+  }
+}
+
+template <int SPLIT, class S>
+__global__ __launch_bounds__(256) void k_adjoint_readout(const typename S::T* __restrict__ state,
+                                                         const double* rb, const double* uxb, const double* uyb,
+                                                         const double* Tb, double* __restrict__ lam, KParams kp) {
+  constexpr int N1 = Set<SPLIT>::N1;
+  constexpr int Q = Set<SPLIT>::Q;
+  const int64_t n = int64_t(kp.nx) * kp.ny;
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x) {
+    const int y = int(k / kp.nx), x = int(k % kp.nx);
+    const int64_t off = int64_t(y) * kp.pitch + x;
+    double f[Q], g[Q], lf[Q], lg[Q];
+    for (int i = 0; i < Q; ++i) {
+      f[i] = decode_one<SPLIT, S>(state[int64_t(i) * kp.plane + off], 0, i, kp);
+      g[i] = decode_one<SPLIT, S>(state[int64_t(Q + i) * kp.plane + off], 1, i, kp);
+    }
+    const NodeMoments m = node_moments<N1>(f, g);
+    readout_adjoint_cell<SPLIT>(m, kp, rb ? rb[k] : 0.0, uxb ? uxb[k] : 0.0, uyb ? uyb[k] : 0.0, Tb ? Tb[k] : 0.0,
+                                lf, lg);
+    for (int i = 0; i < Q; ++i) {
+      lam[int64_t(i) * n + k] = lf[i];
+      lam[int64_t(Q + i) * n + k] = lg[i];
+    }
+  }
+}
+
+template <int SPLIT>
+__global__ __launch_bounds__(256) void k_adjoint_init(const double* __restrict__ lam, const double* __restrict__ rho,
+                                                      const double* __restrict__ ux, const double* __restrict__ uy,
+                                                      const double* __restrict__ T, double* d_rho, double* d_ux,
+                                                      double* d_uy, double* d_T, KParams kp) {
+  constexpr int Q = Set<SPLIT>::Q;
+  const int64_t n = int64_t(kp.nx) * kp.ny;
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x) {
+    const double in[4] = {rho[k], ux[k], uy[k], T[k]};
+    double* outs[4] = {d_rho, d_ux, d_uy, d_T};
+    for (int r = 0; r < 4; ++r) {
+      if (!outs[r]) continue;
+      D1 v[4];
+      for (int j = 0; j < 4; ++j) v[j] = D1(in[j], j == r ? 1.0 : 0.0);
+      D1 f[Q], g[Q];
+      equilibrium_cell<SPLIT, D1>(v[0], v[1], v[2], v[3], kp, f, g);
+      double acc = 0.0;
+      for (int i = 0; i < Q; ++i) acc += lam[int64_t(i) * n + k] * f[i].d + lam[int64_t(Q + i) * n + k] * g[i].d;
+      outs[r][k] = acc;
+    }
+  }
+}
+
 }  // namespace dvbm
 
 // =================================================================== C ABI
@@ -433,6 +505,69 @@ struct EncodeOp {
   }
 };
 
+template <int SPLIT, class S, int BCX, int BCY>
+void launch_adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, double* lam0) {
+  using T = typename S::T;
+  const T* s = static_cast<const T*>(state);
+  const double tau = h->p.tau_ref;
+  const dim3 grid(RED_BLOCKS), block(RED_THREADS);
+  switch (pr_mode(h->p.Pr)) {
+    case PR_UNIT:
+      hipLaunchKernelGGL((k_adjoint_step<SPLIT, S, BCX, BCY, PR_UNIT>), grid, block, 0, h->stream, s, lam1, lam0,
+                         h->kp, tau, h->ws);
+      break;
+    case PR_LOW:
+      hipLaunchKernelGGL((k_adjoint_step<SPLIT, S, BCX, BCY, PR_LOW>), grid, block, 0, h->stream, s, lam1, lam0,
+                         h->kp, tau, h->ws);
+      break;
+    default:
+      hipLaunchKernelGGL((k_adjoint_step<SPLIT, S, BCX, BCY, PR_HIGH>), grid, block, 0, h->stream, s, lam1, lam0,
+                         h->kp, tau, h->ws);
+      break;
+  }
+}
+
+template <int SPLIT, class S>
+struct AdjointOp {
+  static void run(const dvbm_handle* h, const void* state, const double* lam1, double* lam0) {
+    const int bx = h->p.bc_x, by = h->p.bc_y;
+    if (bx == DVBM_PERIODIC && by == DVBM_PERIODIC)
+      launch_adjoint_bc<SPLIT, S, BC_PERIODIC, BC_PERIODIC>(h, state, lam1, lam0);
+    else if (bx == DVBM_ZERO_GRADIENT && by == DVBM_PERIODIC)
+      launch_adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_PERIODIC>(h, state, lam1, lam0);
+    else if (bx == DVBM_PERIODIC && by == DVBM_ZERO_GRADIENT)
+      launch_adjoint_bc<SPLIT, S, BC_PERIODIC, BC_ZERO_GRADIENT>(h, state, lam1, lam0);
+    else
+      launch_adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_ZERO_GRADIENT>(h, state, lam1, lam0);
+  }
+};
+
+template <int SPLIT, class S>
+struct ReadoutAdjointOp {
+  static void run(const dvbm_handle* h, const void* state, const double* rb, const double* uxb, const double* uyb,
+                  const double* Tb, double* lam) {
+    using Tt = typename S::T;
+    hipLaunchKernelGGL((k_adjoint_readout<SPLIT, S>), dim3(RED_BLOCKS), dim3(256), 0, h->stream,
+                       static_cast<const Tt*>(state), rb, uxb, uyb, Tb, lam, h->kp);
+  }
+};
+
+// The adjoint entry points support the float64 and float32 storages.
+template <template <int, class> class F, class... A>
+void dispatch_adjoint(const dvbm_params& p, A&&... args) {
+  if (p.split == 2) {
+    if (p.storage == DVBM_F64)
+      F<2, StoreF64>::run(args...);
+    else
+      F<2, StoreF32>::run(args...);
+  } else {
+    if (p.storage == DVBM_F64)
+      F<1, StoreF64>::run(args...);
+    else
+      F<1, StoreF32>::run(args...);
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -607,5 +742,53 @@ int dvbm_set_state_index(dvbm_handle* h, int index) {
 void dvbm_destroy(dvbm_handle* h) { delete h; }
 
 const char* dvbm_last_error(void) { return g_last_error.c_str(); }
+
+size_t dvbm_adjoint_bytes(const dvbm_params* p) {
+  if (!check_params(p).empty()) return 0;
+  const int Q = p->split == 1 ? 16 : 25;
+  return size_t(2) * Q * size_t(p->ny) * size_t(p->nx) * sizeof(double);
+}
+
+static int adjoint_storage_ok(const dvbm_handle* h, const char* who) {
+  if (h->p.storage != DVBM_F64 && h->p.storage != DVBM_F32)
+    return fail(DVBM_EINVAL, std::string(who) + ": the adjoint supports f64 and f32 storage");
+  return DVBM_OK;
+}
+
+int dvbm_adjoint_step(dvbm_handle* h, const void* state_n, const double* lam_np1, double* lam_n, double* dparams) {
+  if (!h || !state_n || !lam_np1 || !lam_n) return fail(DVBM_EINVAL, "dvbm_adjoint_step: NULL argument");
+  if (lam_np1 == lam_n) return fail(DVBM_EINVAL, "dvbm_adjoint_step: lam_np1 and lam_n must differ");
+  if (int rc = adjoint_storage_ok(h, "dvbm_adjoint_step")) return rc;
+  dispatch_adjoint<AdjointOp>(h->p, h, state_n, lam_np1, lam_n);
+  if (dparams) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, h->stream, h->ws, RED_BLOCKS, 0,
+                       h->ws + 4 * RED_BLOCKS);
+    hipLaunchKernelGGL(k_accumulate2, dim3(1), dim3(64), 0, h->stream, h->ws + 4 * RED_BLOCKS, dparams);
+  }
+  HIP_TRY(hipGetLastError());
+  return DVBM_OK;
+}
+
+int dvbm_adjoint_moments(dvbm_handle* h, const void* state, const double* d_rho, const double* d_ux,
+                         const double* d_uy, const double* d_T, double* lam) {
+  if (!h || !state || !lam) return fail(DVBM_EINVAL, "dvbm_adjoint_moments: NULL argument");
+  if (int rc = adjoint_storage_ok(h, "dvbm_adjoint_moments")) return rc;
+  dispatch_adjoint<ReadoutAdjointOp>(h->p, h, state, d_rho, d_ux, d_uy, d_T, lam);
+  HIP_TRY(hipGetLastError());
+  return DVBM_OK;
+}
+
+int dvbm_adjoint_init(dvbm_handle* h, const double* lam0, const double* rho, const double* ux, const double* uy,
+                      const double* T, double* d_rho, double* d_ux, double* d_uy, double* d_T) {
+  if (!h || !lam0 || !rho || !ux || !uy || !T) return fail(DVBM_EINVAL, "dvbm_adjoint_init: NULL argument");
+  if (h->p.split == 2)
+    hipLaunchKernelGGL(k_adjoint_init<2>, dim3(RED_BLOCKS), dim3(256), 0, h->stream, lam0, rho, ux, uy, T, d_rho,
+                       d_ux, d_uy, d_T, h->kp);
+  else
+    hipLaunchKernelGGL(k_adjoint_init<1>, dim3(RED_BLOCKS), dim3(256), 0, h->stream, lam0, rho, ux, uy, T, d_rho,
+                       d_ux, d_uy, d_T, h->kp);
+  HIP_TRY(hipGetLastError());
+  return DVBM_OK;
+}
 
 }  // extern "C"

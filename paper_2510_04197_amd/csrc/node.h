@@ -130,10 +130,13 @@ __device__ inline void pair_sums(const V* v, double& s0, double& s1, double& s2,
 }
 
 // Raw moments in normalised velocity units (v = sqrt(R T_ref) xi).
-struct NodeMoments {
-  double rho, jx, jy, pxx, pxy, pyy, qxxx, qxxy, qxyy, qyyy;  // f: orders 0..3
-  double g0, qgx, qgy;                                         // g: orders 0..1
+template <class V>
+struct MomentsT {
+  V rho, jx, jy, pxx, pxy, pyy, qxxx, qxxy, qxyy, qyyy;  // f: orders 0..3
+  V g0, qgx, qgy;                                         // g: orders 0..1
 };
+using NodeMoments = MomentsT<double>;
+constexpr int N_MOMENTS = 13;
 
 // Eqs. (eq_quadratur1-3) and the moment notation of Table I, in float64.
 template <int N1, class R>
@@ -172,27 +175,31 @@ __device__ inline void gauss_hermite_moments(R u, R t, R* m) {
 // Collision coefficients of one node:  X_new = (1 - om1) X + w_i sum_k b_k H_k(i) / (p! q!)
 // with b = om1 a^eq + (om1 - om2) (a* - a^eq)  (Eq. finalDiscretePDE).
 // bf[p][q], bg[p][q] are in normalised units (a_n / sqrt(R T_ref)^n).
-template <int SPLIT, int PRM, class R>
-__device__ inline void collision_coeffs(const NodeMoments& m, const KParams& kp, R (&bf)[5][5], R (&bg)[3][3],
-                                        R& om1_out) {
-  const double rho = m.rho;
-  const double irho = 1.0 / rho;
-  const double ux = m.jx * irho, uy = m.jy * irho;
-  const double E = SPLIT == 2 ? m.g0 + 0.5 * kp.c2 * (m.pxx + m.pyy) : m.g0;
-  const double T = (E * irho - 0.5 * kp.c2 * (ux * ux + uy * uy)) * kp.inv_Cv;
-  const double RT = kp.R * T;
-  const double th = RT / kp.c2;
-  const double p = rho * RT;
+// V is the type of the intermediate (moment-level) arithmetic: float64 in the
+// step kernels, a dual number in the adjoint kernel; om_scale and Pr are
+// passed separately so that the adjoint can differentiate with respect to
+// them (kp.om_scale and kp.Pr in the step kernels).
+template <int SPLIT, int PRM, class R, class V = double>
+__device__ inline void collision_coeffs(const MomentsT<V>& m, const KParams& kp, V om_scale, V Pr,
+                                        R (&bf)[5][5], R (&bg)[3][3], R& om1_out) {
+  const V rho = m.rho;
+  const V irho = 1.0 / rho;
+  const V ux = m.jx * irho, uy = m.jy * irho;
+  const V E = SPLIT == 2 ? m.g0 + 0.5 * kp.c2 * (m.pxx + m.pyy) : m.g0;
+  const V T = (E * irho - 0.5 * kp.c2 * (ux * ux + uy * uy)) * kp.inv_Cv;
+  const V RT = kp.R * T;
+  const V th = RT / kp.c2;
+  const V p = rho * RT;
 
   // omega = dt / tau (Sec. II C): tau_nu = mu / p or fixed; tau_alpha = tau_nu / Pr.
-  const R omn = R(kp.const_mu ? kp.om_scale * p : kp.om_scale);
+  const R omn = R(kp.const_mu ? V(om_scale * p) : om_scale);
   R om1, om2;
   if (PRM == PR_HIGH) {
-    om1 = omn * R(kp.Pr);
+    om1 = omn * R(Pr);
     om2 = omn;
   } else {
     om1 = omn;
-    om2 = PRM == PR_LOW ? omn * R(kp.Pr) : omn;
+    om2 = PRM == PR_LOW ? omn * R(Pr) : omn;
   }
   om1_out = om1;
   const R dw = om1 - om2;
@@ -233,34 +240,34 @@ __device__ inline void collision_coeffs(const NodeMoments& m, const KParams& kp,
   if (PRM == PR_UNIT) return;  // Table I: f* = f^eq, g* = g^eq
 
   // Non-equilibrium second moment, Delta P = M2(f) - M2(f^eq), in float64.
-  const double dxx = m.pxx - rho * (ux * ux + th);
-  const double dxy = m.pxy - rho * ux * uy;
-  const double dyy = m.pyy - rho * (uy * uy + th);
+  const V dxx = m.pxx - rho * (ux * ux + th);
+  const V dxy = m.pxy - rho * ux * uy;
+  const V dyy = m.pyy - rho * (uy * uy + th);
 
   if (SPLIT == 2) {
     if (PRM == PR_LOW) {
       // M3* = M3(f) - S(u, Delta P),  S = [u A]_cyc - tr A / (D + 2) [u delta]_cyc;  M1(g*) = M1(g).
-      const double tr4 = 0.25 * (dxx + dyy);
-      const double Sxxx = 3.0 * ux * dxx - 3.0 * tr4 * ux;
-      const double Sxxy = 2.0 * ux * dxy + uy * dxx - tr4 * uy;
-      const double Sxyy = 2.0 * uy * dxy + ux * dyy - tr4 * ux;
-      const double Syyy = 3.0 * uy * dyy - 3.0 * tr4 * uy;
-      const double rt = rho * th;
-      const double eqxxx = rho * ux * ux * ux + 3.0 * rt * ux;
-      const double eqxxy = rho * ux * ux * uy + rt * uy;
-      const double eqxyy = rho * ux * uy * uy + rt * ux;
-      const double eqyyy = rho * uy * uy * uy + 3.0 * rt * uy;
+      const V tr4 = 0.25 * (dxx + dyy);
+      const V Sxxx = 3.0 * ux * dxx - 3.0 * tr4 * ux;
+      const V Sxxy = 2.0 * ux * dxy + uy * dxx - tr4 * uy;
+      const V Sxyy = 2.0 * uy * dxy + ux * dyy - tr4 * ux;
+      const V Syyy = 3.0 * uy * dyy - 3.0 * tr4 * uy;
+      const V rt = rho * th;
+      const V eqxxx = rho * ux * ux * ux + 3.0 * rt * ux;
+      const V eqxxy = rho * ux * ux * uy + rt * uy;
+      const V eqxyy = rho * ux * uy * uy + rt * ux;
+      const V eqyyy = rho * uy * uy * uy + 3.0 * rt * uy;
       bf[3][0] += dw * R(m.qxxx - eqxxx - Sxxx);
       bf[2][1] += dw * R(m.qxxy - eqxxy - Sxxy);
       bf[1][2] += dw * R(m.qxyy - eqxyy - Sxyy);
       bf[0][3] += dw * R(m.qyyy - eqyyy - Syyy);
-      const double e = rho * (kp.Cv - kp.R) * T;
+      const V e = rho * (kp.Cv - kp.R) * T;
       bg[1][0] += dw * R(m.qgx - e * ux);
       bg[0][1] += dw * R(m.qgy - e * uy);
     } else {
       // M2* = M2(f) - tr(Delta P)/D delta, M3* = M3(f^eq) + [u Delta P']_cyc,
       // a4* = a4^eq - [(a2* - a2^eq) delta]_cyc; g* = g^eq.
-      const double h = 0.5 * (dxx + dyy);
+      const V h = 0.5 * (dxx + dyy);
       const R axx = R(dxx - h), axy = R(dxy), ayy = R(dyy - h);
       const R rux = R(ux), ruy = R(uy);
       bf[2][0] += dw * axx;
@@ -278,10 +285,10 @@ __device__ inline void collision_coeffs(const NodeMoments& m, const KParams& kp,
     }
   } else {
     // split I:  u . Delta P  enters the heat flux of g*.
-    const double upx = ux * dxx + uy * dxy, upy = ux * dxy + uy * dyy;
+    const V upx = ux * dxx + uy * dxy, upy = ux * dxy + uy * dyy;
     if (PRM == PR_LOW) {
       // f* = f^eq;  M1(g*) = M1(g) - u . Delta P
-      const double Ep = E + p;
+      const V Ep = E + p;
       bg[1][0] += dw * R(m.qgx - kp.c2 * upx - ux * Ep);
       bg[0][1] += dw * R(m.qgy - kp.c2 * upy - uy * Ep);
     } else {

@@ -140,7 +140,7 @@ __device__ inline void cell_update(const typename S::T* __restrict__ src, typena
   }
   const NodeMoments m = node_moments<N1>(X[0], X[1]);
   R bf[5][5], bg[3][3], om1;
-  collision_coeffs<SPLIT, PRM, R>(m, kp, bf, bg, om1);
+  collision_coeffs<SPLIT, PRM, R>(m, kp, kp.om_scale, kp.Pr, bf, bg, om1);
 
   // collision: (1 - om1) X + expansion of b
   const R keep = R(1) - om1;
@@ -292,7 +292,7 @@ __device__ inline void tile_update(const typename S::T* __restrict__ src, typena
     m = node_moments<N1>(f, g);
   }
   R bf[5][5], bg[3][3], om1;
-  collision_coeffs<SPLIT, PRM, R>(m, kp, bf, bg, om1);
+  collision_coeffs<SPLIT, PRM, R>(m, kp, kp.om_scale, kp.Pr, bf, bg, om1);
   const R keep = R(1) - om1;
   const R beta2 = R(kp.beta2);
   const R kx = R(kp.kx), ky = R(kp.ky);

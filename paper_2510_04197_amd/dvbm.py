@@ -62,6 +62,10 @@ SIGNATURES = {
     "dvbm_state_index": (ctypes.c_int, [_P]),
     "dvbm_set_state_index": (ctypes.c_int, [_P, ctypes.c_int]),
     "dvbm_destroy": (None, [_P]),
+    "dvbm_adjoint_bytes": (ctypes.c_size_t, [_PP]),
+    "dvbm_adjoint_step": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "dvbm_adjoint_moments": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "dvbm_adjoint_init": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "dvbm_last_error": (ctypes.c_char_p, []),
 }
 
@@ -209,6 +213,36 @@ class Solver:
         _check(self.lib.dvbm_store_populations(self.handle, _ptr(X)))
         self.stream.synchronize()
         return X
+
+    # ------------------------------------------------------------------ adjoint
+    def new_cotangent(self) -> torch.Tensor:
+        """A zeroed dense float64 cotangent ``[2, Q, ny, nx]``."""
+        return torch.zeros((2, self.Q, self.params.ny, self.params.nx), dtype=torch.float64, device=self.device)
+
+    def adjoint_step(self, state: torch.Tensor, lam_next: torch.Tensor, lam: torch.Tensor,
+                     dparams: torch.Tensor | None = None):
+        """``lam = (dX'/dX)^T lam_next`` at ``state``; ``dparams`` (float64[2]) += (d/dtau_ref, d/dPr)."""
+        _check(self.lib.dvbm_adjoint_step(self.handle, _ptr(state), _ptr(lam_next), _ptr(lam),
+                                          _ptr(dparams) if dparams is not None else None))
+
+    def adjoint_moments(self, state: torch.Tensor, d_rho=None, d_ux=None, d_uy=None, d_T=None) -> torch.Tensor:
+        """Cotangent of the populations of ``state`` from cotangents of its fields."""
+        lam = self.new_cotangent()
+        cot = [None if a is None else _dev_f64(a, self.device) for a in (d_rho, d_ux, d_uy, d_T)]
+        _check(self.lib.dvbm_adjoint_moments(self.handle, _ptr(state), *[_ptr(a) if a is not None else None
+                                                                          for a in cot], _ptr(lam)))
+        self._keep = cot
+        return lam
+
+    def adjoint_init(self, lam0: torch.Tensor, rho, ux, uy, T, which=("T",)):
+        """Cotangents of the initial fields named in ``which`` (subset of rho, ux, uy, T)."""
+        fields = [_dev_f64(a, self.device) for a in (rho, ux, uy, T)]
+        names = ("rho", "ux", "uy", "T")
+        outs = {k: torch.zeros_like(fields[0]) for k in which}
+        _check(self.lib.dvbm_adjoint_init(self.handle, _ptr(lam0), *[_ptr(f) for f in fields],
+                                          *[_ptr(outs[k]) if k in outs else None for k in names]))
+        self.stream.synchronize()
+        return outs
 
     def close(self):
         if getattr(self, "handle", None):
