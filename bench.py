@@ -93,7 +93,9 @@ def time_mode(wl, phys, storage, steps, warmup, device):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
-    sums = s.moments(fields=False)["sums"]
+    mom = s.moments(fields=True)
+    sums = mom["sums"]
+    fields = {"rho": mom["rho"], "T": mom["T"]}
     Q = s.Q
     cells = wl.nx * wl.ny
     bytes_per_update = 2 * (2 * Q) * STORAGE_BYTES[storage]
@@ -112,7 +114,74 @@ def time_mode(wl, phys, storage, steps, warmup, device):
     s.close()
     del s
     torch.cuda.empty_cache()
+    return out, fields
+
+
+def precision_errors(fields, ref):
+    """Relative L2 errors of rho and T against the float64-storage run of the same steps."""
+    import torch
+
+    out = {}
+    for k in ("rho", "T"):
+        out[f"rel_L2_{k}"] = float(torch.linalg.vector_norm(fields[k] - ref[k]) / torch.linalg.vector_norm(ref[k]))
+        dev = ref[k] - ref[k].mean()
+        out[f"rel_L2_{k}_of_variation"] = float(torch.linalg.vector_norm(fields[k] - ref[k])
+                                                / torch.linalg.vector_norm(dev))
     return out
+
+
+def adjoint_cost(device, n=256, nsteps=200, storage="f32", Ks=(10, 50)):
+    """Gradient of L = sum (T(200 steps) - T_target)^2 w.r.t. T0, tau_ref, Pr on the 256^2 periodic
+    Gaussian-bump workload: time of forward + checkpointed recomputation + reverse sweep, divided by
+    the time of the plain forward run."""
+    import numpy as np
+    import torch
+
+    from paper_2510_04197_amd import Solver, make_params, rollout_temperature
+    from synth import gaussian_bump, smooth_random
+
+    bump = gaussian_bump(n, seed=7, amp=0.1, width=0.1)
+    T0 = smooth_random(n, n, seed=13, amp_rho=0.0, amp_u=0.0, amp_T=0.05, mean_u=(0.0, 0.0)).T
+    ones, zeros = np.ones((n, n)), np.zeros((n, n))
+    kw = dict(dx=1.0 / n, dy=1.0 / n, split=2, storage=storage, dt=1e-4)
+    tau0, Pr = 2e-3, 0.71
+    tgt = rollout_temperature(torch.tensor(bump.T, device=device), torch.tensor(tau0, dtype=torch.float64),
+                              torch.tensor(Pr, dtype=torch.float64), ones, zeros, zeros, nsteps, K=50,
+                              **kw).detach()
+    p = make_params(n, n, tau_ref=tau0, Pr=Pr, **kw)
+
+    def forward_only():
+        s = Solver(p, ones, zeros, zeros, T0, device=device)
+        s.step(nsteps)
+        T = s.moments(fields=True, sums=False)["T"]
+        s.close()
+        return T
+
+    def with_gradient(K):
+        T0t = torch.tensor(T0, device=device, requires_grad=True)
+        tau = torch.tensor(tau0, dtype=torch.float64, requires_grad=True)
+        prt = torch.tensor(Pr, dtype=torch.float64, requires_grad=True)
+        out = rollout_temperature(T0t, tau, prt, ones, zeros, zeros, nsteps, K=K, **kw)
+        ((out - tgt) ** 2).sum().backward()
+        return T0t.grad
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_fwd = timed(forward_only)
+    res = {"workload": f"gaussian bump {n}x{n} periodic, {nsteps} steps, {storage} storage",
+           "forward_s": t_fwd}
+    for K in Ks:
+        t = timed(lambda: with_gradient(K))
+        res[f"K{K}_s"] = t
+        res[f"K{K}_ratio"] = t / t_fwd
+    return res
 
 
 def copy_bandwidth(device, nbytes=4 << 30, reps=5):
@@ -135,7 +204,7 @@ def copy_bandwidth(device, nbytes=4 << 30, reps=5):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(n=384, steps=24):
+def cpu_baseline(n=512, steps=40):
     """The FP64 oracle on the host: same workload family on an n x n sample."""
     import numpy as np
     import torch
@@ -165,6 +234,7 @@ def main():
     ap.add_argument("--modes", default="f64,bf16_dev,fp16_dev",
                     help="extra storages timed after the main one ('none' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -182,15 +252,28 @@ def main():
     print(f"[bench] workload {args.workload}, storage {args.storage}, steps {args.steps}, warmup {args.warmup}",
           file=sys.stderr, flush=True)
     wl, phys = workload_fields(args.workload)
-    main = time_mode(wl, phys, args.storage, args.steps, args.warmup, device)
+    main, main_fields = time_mode(wl, phys, args.storage, args.steps, args.warmup, device)
     print(f"[bench] {args.storage}: {main['MLUPS']:.1f} MLUPS, {main['GBps']:.1f} GB/s", file=sys.stderr, flush=True)
     modes = {}
+    fields = {args.storage: main_fields}
     if args.modes != "none":
         for st in args.modes.split(","):
             if st and st != args.storage:
-                modes[st] = time_mode(wl, phys, st, args.steps, args.warmup, device)
+                modes[st], fields[st] = time_mode(wl, phys, st, args.steps, args.warmup, device)
                 print(f"[bench] {st}: {modes[st]['MLUPS']:.1f} MLUPS, {modes[st]['GBps']:.1f} GB/s",
                       file=sys.stderr, flush=True)
+    precision = None
+    if "f64" in fields:
+        precision = {"reference": "float64-storage GPU run of the same workload and step count",
+                     "steps": args.warmup + args.steps}
+        for st, fl in fields.items():
+            if st != "f64":
+                precision[st] = precision_errors(fl, fields["f64"])
+    del fields, main_fields
+    adjoint = None
+    if not args.no_adjoint:
+        print("[bench] adjoint cost on the 256x256 gradient workload", file=sys.stderr, flush=True)
+        adjoint = adjoint_cost(device)
     copy_gbps = copy_bandwidth(device)
     if args.copy_calibration:
         a = torch.empty(1 << 30, dtype=torch.uint8, device=device)
@@ -228,8 +311,10 @@ def main():
                    "Pr": phys["Pr"], "gamma": phys["gamma"], "bc": [phys["bc_x"], phys["bc_y"]]},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "modes": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+        "modes": {k: {kk: (float("%.5g" % vv) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                   for k, v in modes.items()},
+        "precision": precision,
+        "adjoint": adjoint,
     }
     print(json.dumps(line), flush=True)
 

@@ -35,20 +35,58 @@ namespace dvbm {
 //    path the bottleneck).
 constexpr int RED_BLOCKS = 1024;
 constexpr int RED_THREADS = 256;
-constexpr int CELL_TX = 64, CELL_TY = 4;  // per-cell kernel: 64 x 4 cells per workgroup
-constexpr int TILE_TX = 64, TILE_TY = 4;  // LDS kernel tile
+#ifndef DVBM_CELL_TX
+#define DVBM_CELL_TX 64
+#endif
+#ifndef DVBM_CELL_TY
+#define DVBM_CELL_TY 4
+#endif
+#ifndef DVBM_TILE_TX
+#define DVBM_TILE_TX 64
+#endif
+#ifndef DVBM_TILE_TY
+#define DVBM_TILE_TY 4
+#endif
+#ifndef DVBM_ORDER
+#define DVBM_ORDER 0
+#endif
+constexpr int CELL_TX = DVBM_CELL_TX, CELL_TY = DVBM_CELL_TY;  // per-cell kernel workgroup tile
+constexpr int TILE_TX = DVBM_TILE_TX, TILE_TY = DVBM_TILE_TY;  // LDS kernel tile
 
+// Tile (bx, by) of linear workgroup w.  Consecutive workgroups are dealt
+// round-robin to the 8 XCDs, each with its own L2.  ORDER 0 keeps the plain
+// row-major order; ORDER 2 gives every XCD one contiguous range of tiles in
+// column-major order, so that the tiles above and below a tile (which read
+// its rows as ghost layers) run on the same XCD right after it.
+__device__ inline void tile_of_block(int w, int nbx, int nby, int& bx, int& by) {
+  if (DVBM_ORDER == 0) {
+    bx = w % nbx;
+    by = w / nbx;
+    return;
+  }
+  const int total = nbx * nby;
+  const int xcd = w % 8, k = w / 8, base = total / 8, rem = total % 8;
+  const int t = xcd < rem ? xcd * (base + 1) + k : rem * (base + 1) + (xcd - rem) * base + k;
+  bx = t / nby;
+  by = t % nby;
+}
+
+#ifndef DVBM_LDS_ALL
+#define DVBM_LDS_ALL 0
+#endif
 template <class S>
 struct UseTiles {
-  static constexpr bool value = sizeof(typename S::T) == 8;
+  static constexpr bool value = DVBM_LDS_ALL || sizeof(typename S::T) == 8;
 };
 
 // ------------------------------------------------------------ fused step
 template <int SPLIT, class S, int BCX, int BCY, int PRM>
 __global__ __launch_bounds__(CELL_TX* CELL_TY) void k_collide_advect(const typename S::T* __restrict__ src,
                                                                      typename S::T* __restrict__ dst, KParams kp) {
-  const int x = blockIdx.x * CELL_TX + threadIdx.x;
-  const int y = blockIdx.y * CELL_TY + threadIdx.y;
+  int bx, by;
+  tile_of_block(blockIdx.x, (kp.nx + CELL_TX - 1) / CELL_TX, (kp.ny + CELL_TY - 1) / CELL_TY, bx, by);
+  const int x = bx * CELL_TX + threadIdx.x;
+  const int y = by * CELL_TY + threadIdx.y;
   if (x >= kp.nx || y >= kp.ny) return;
   cell_update<SPLIT, S, BCX, BCY, PRM>(src, dst, kp, x, y);
 }
@@ -58,7 +96,9 @@ __global__ __launch_bounds__(TILE_TX* TILE_TY) void k_collide_advect_lds(const t
                                                                          typename S::T* __restrict__ dst,
                                                                          KParams kp) {
   __shared__ PlaneTile<typename S::C, TILE_TX, TILE_TY, Set<SPLIT>::N1> lds;
-  tile_update<SPLIT, S, BCX, BCY, PRM, TILE_TX, TILE_TY>(src, dst, kp, blockIdx.x, blockIdx.y, lds);
+  int bx, by;
+  tile_of_block(blockIdx.x, (kp.nx + TILE_TX - 1) / TILE_TX, (kp.ny + TILE_TY - 1) / TILE_TY, bx, by);
+  tile_update<SPLIT, S, BCX, BCY, PRM, TILE_TX, TILE_TY>(src, dst, kp, bx, by, lds);
 }
 
 // ------------------------------------------------------------ equilibrium initialisation
@@ -408,11 +448,11 @@ void launch_step_pr(const dvbm_handle* h, const void* src, void* dst) {
   const T* s = static_cast<const T*>(src);
   T* d = static_cast<T*>(dst);
   if constexpr (UseTiles<S>::value) {
-    const dim3 grid((h->p.nx + TILE_TX - 1) / TILE_TX, (h->p.ny + TILE_TY - 1) / TILE_TY);
+    const dim3 grid(((h->p.nx + TILE_TX - 1) / TILE_TX) * ((h->p.ny + TILE_TY - 1) / TILE_TY));
     hipLaunchKernelGGL((k_collide_advect_lds<SPLIT, S, BCX, BCY, PRM>), grid, dim3(TILE_TX, TILE_TY), 0, h->stream,
                        s, d, h->kp);
   } else {
-    const dim3 grid((h->p.nx + CELL_TX - 1) / CELL_TX, (h->p.ny + CELL_TY - 1) / CELL_TY);
+    const dim3 grid(((h->p.nx + CELL_TX - 1) / CELL_TX) * ((h->p.ny + CELL_TY - 1) / CELL_TY));
     hipLaunchKernelGGL((k_collide_advect<SPLIT, S, BCX, BCY, PRM>), grid, dim3(CELL_TX, CELL_TY), 0, h->stream, s,
                        d, h->kp);
   }

@@ -272,21 +272,25 @@ __device__ inline void tile_update(const typename S::T* __restrict__ src, typena
   const rsrc_t rsrc_src[2] = {dist_rsrc(src, 0, dist_bytes), dist_rsrc(src, 1, dist_bytes)};
   const rsrc_t rsrc_dst[2] = {dist_rsrc(dst, 0, dist_bytes), dist_rsrc(dst, 1, dist_bytes)};
 
-  // Pass 1: the cell's populations and their float64 moments.
+  // Pass 1: the cell's populations (kept in registers for pass 2) and their
+  // float64 moments.
+  R xs[2][Q];
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) xs[d][i] = S::raw(Buf<T>::ld(rsrc_src[d], i * plane_bytes, o0));
   NodeMoments m;
   {
     R f[Q], g[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const R rf = S::raw(Buf<T>::ld(rsrc_src[0], i * plane_bytes, o0));
-      const R rg = S::raw(Buf<T>::ld(rsrc_src[1], i * plane_bytes, o0));
       if (S::dev) {
         const double w = weight<SPLIT>(i);
-        f[i] = R(w) * (R(1) + rf);
-        g[i] = R(w) * (R(g_ref_over_w<SPLIT>(kp, i)) + rg);
+        f[i] = R(w) * (R(1) + xs[0][i]);
+        g[i] = R(w) * (R(g_ref_over_w<SPLIT>(kp, i)) + xs[1][i]);
       } else {
-        f[i] = rf;
-        g[i] = rg;
+        f[i] = xs[0][i];
+        g[i] = xs[1][i];
       }
     }
     m = node_moments<N1>(f, g);
@@ -296,9 +300,6 @@ __device__ inline void tile_update(const typename S::T* __restrict__ src, typena
   const R keep = R(1) - om1;
   const R beta2 = R(kp.beta2);
   const R kx = R(kp.kx), ky = R(kp.ky);
-  // Pass 2 re-reads each population (a cache hit) rather than pinning all 2Q
-  // of them in registers.
-  __asm__ volatile("" ::: "memory");
 
   // Pass 2: groups gk = d N1 + b of the N1 populations i = a N1 + b that share
   // the y-node b (so the Grad expansion factors into
@@ -308,18 +309,17 @@ __device__ inline void tile_update(const typename S::T* __restrict__ src, typena
   constexpr int PL = (TY + 4) * W;
   constexpr int NMAX = 4;
   const int me = (ty + 2) * W + tx + 2;
-  R cur[N1], curh[N1][H];
-  auto fetch = [&](int gk, R (&c)[N1], R (&h)[N1][H]) {
+  R curh[N1][H];
+  auto fetch = [&](int gk, R (&h)[N1][H]) {
     const int d = gk / N1, yb = gk % N1;
 #pragma unroll
     for (int xa = 0; xa < N1; ++xa) {
       const uint32_t so = (xa * N1 + yb) * plane_bytes;
-      c[xa] = S::raw(Buf<T>::ld(rsrc_src[d], so, o0));
 #pragma unroll
       for (int j = 0; j < H; ++j) h[xa][j] = hval[j] ? S::raw(Buf<T>::ld(rsrc_src[d], so, hoff[j])) : R(0);
     }
   };
-  fetch(0, cur, curh);
+  fetch(0, curh);
   static_for<2 * N1>([&](auto gc) {
     constexpr int gk = decltype(gc)::value;
     constexpr int d = gk / N1, yb = gk % N1;
@@ -336,17 +336,15 @@ __device__ inline void tile_update(const typename S::T* __restrict__ src, typena
         if (h != 0.0) c[p] += (d == 0 ? bf[p][q] : bg[p][q]) * R(h);
       }
     }
-    R c0s[N1];
 #pragma unroll
     for (int xa = 0; xa < N1; ++xa) {
       R* buf = &lds.v[gk & 1][xa][0][0];
-      c0s[xa] = cur[xa];
-      buf[me] = cur[xa];
+      buf[me] = xs[d][xa * N1 + yb];
 #pragma unroll
       for (int j = 0; j < H; ++j)
         if (hval[j]) buf[hidx[j]] = curh[xa][j];
     }
-    if (gk + 1 < 2 * N1) fetch(gk + 1, cur, curh);
+    if (gk + 1 < 2 * N1) fetch(gk + 1, curh);
     __syncthreads();
 
     static_for<N1>([&](auto ac) {
@@ -355,7 +353,7 @@ __device__ inline void tile_update(const typename S::T* __restrict__ src, typena
       constexpr double xv = L::xi(xa);
       constexpr double w = GH<N1>::w(xa) * GH<N1>::w(yb);
       const R* buf = &lds.v[gk & 1][xa][0][0];
-      const R c0 = c0s[xa];
+      const R c0 = xs[d][i];
       const uint32_t so = i * plane_bytes;
       const R rr = S::dev ? R(d == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i)) : R(0);
       const R X = S::dev ? R(w) * (rr + c0) : c0;
