@@ -22,6 +22,7 @@
 #include "lattice.h"
 #include "node.h"
 #include "step.h"
+#include "sweep.h"
 #include "adjoint.h"
 
 namespace dvbm {
@@ -71,6 +72,9 @@ __device__ inline void tile_of_block(int w, int nbx, int nby, int& bx, int& by) 
   by = t % nby;
 }
 
+#ifndef DVBM_SWEEP
+#define DVBM_SWEEP 1
+#endif
 #ifndef DVBM_LDS_ALL
 #define DVBM_LDS_ALL 0
 #endif
@@ -99,6 +103,51 @@ __global__ __launch_bounds__(TILE_TX* TILE_TY) void k_collide_advect_lds(const t
   int bx, by;
   tile_of_block(blockIdx.x, (kp.nx + TILE_TX - 1) / TILE_TX, (kp.ny + TILE_TY - 1) / TILE_TY, bx, by);
   tile_update<SPLIT, S, BCX, BCY, PRM, TILE_TX, TILE_TY>(src, dst, kp, bx, by, lds);
+}
+
+// Row range j of kseg in a column of ny rows for the column sweep: ranges of
+// 3 m rows (m >= 1, 3 m <= ny) from the top; the last one is moved up so
+// that it ends at row ny and may overlap its predecessor (rows computed by
+// both ranges get identical values).  Requires ny >= 3 and
+// kseg = sweep_count(ny, ...).
+__host__ __device__ inline int sweep_len(int ny, int want) {
+  int len = 3 * ((ny + 3 * want - 1) / (3 * want));
+  const int cap = 3 * (ny / 3);
+  return len < cap ? len : cap;
+}
+__device__ inline void sweep_range(int ny, int kseg, int j, int& ya, int& yb) {
+  const int len = sweep_len(ny, kseg);
+  ya = j * len;
+  if (ya > ny - len) ya = ny - len;
+  yb = ya + len;
+}
+
+// Column sweep (32/16-bit storage): workgroups of 2 SWEEP_K waves, wave w
+// advancing distribution w / SWEEP_K (0: f, 1: g) of strip
+// sg * SWEEP_K + w % SWEEP_K; workgroup b is logical (strip group, row range)
+// L, dealt so that every XCD gets one contiguous range of L;
+// L = j * ngroups + sg covers strip group sg, row range j.
+#ifndef DVBM_SWEEP_WPE
+#define DVBM_SWEEP_WPE 2
+#endif
+template <int SPLIT, class S, int BCX, int BCY, int PRM>
+__global__ __launch_bounds__(128 * SWEEP_K) __attribute__((amdgpu_waves_per_eu(DVBM_SWEEP_WPE))) void
+k_collide_advect_sweep(const typename S::T* __restrict__ src, typename S::T* __restrict__ dst, KParams kp,
+                       int ngroups, int kseg) {
+  __shared__ SweepShared sh[SWEEP_K];
+  const int total = ngroups * kseg;
+  const int per = (total + 7) / 8;
+  const int L = int(blockIdx.x % 8) * per + int(blockIdx.x / 8);
+  if (L >= total) return;
+  const int j = L / ngroups, sg = L % ngroups;
+  int ya, yb;
+  sweep_range(kp.ny, kseg, j, ya, yb);
+  const int w = int(threadIdx.x) / 64, k = w % SWEEP_K;
+  const int x0 = (sg * SWEEP_K + k) * SWEEP_OWN;  // may lie beyond nx: then the wave stores nothing
+  if (w < SWEEP_K)
+    sweep_update<SPLIT, S, BCX, BCY, PRM, 0>(src, dst, kp, x0, ya, yb, sh[k]);
+  else
+    sweep_update<SPLIT, S, BCX, BCY, PRM, 1>(src, dst, kp, x0, ya, yb, sh[k]);
 }
 
 // ------------------------------------------------------------ equilibrium initialisation
@@ -243,6 +292,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_moments(const typename S::T* __
   block_reduce4(acc, mode, partials + 4 * blockIdx.x);
 }
 
+#ifndef DVBM_PART  // non-template kernel: main unit only
 __global__ __launch_bounds__(RED_THREADS) void k_speed(const double* __restrict__ rho, const double* __restrict__ ux,
                                                        const double* __restrict__ uy, const double* __restrict__ T,
                                                        int64_t n, double gR, double R, double* partials) {
@@ -261,7 +311,9 @@ __global__ __launch_bounds__(RED_THREADS) void k_speed(const double* __restrict_
   const int mode[4] = {1, 1, 1, 1};
   block_reduce4(v, mode, partials + 4 * blockIdx.x);
 }
+#endif
 
+#ifndef DVBM_PART  // non-template kernel: main unit only
 __global__ __launch_bounds__(RED_THREADS) void k_reduce(const double* __restrict__ partials, int nblocks, int modesel,
                                                         double* out) {
   double v[4];
@@ -274,6 +326,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(const double* __restrict
     for (int k = 0; k < 4; ++k) v[k] = modesel == 0 ? v[k] + partials[4 * b + k] : fmax(v[k], partials[4 * b + k]);
   block_reduce4(v, mode, out);
 }
+#endif
 
 // ------------------------------------------------------------ adjoint
 template <int SPLIT, class S, int BCX, int BCY, int PRM>
@@ -291,12 +344,14 @@ __global__ __launch_bounds__(RED_THREADS) void k_adjoint_step(const typename S::
   block_reduce4(acc, mode, partials + 4 * blockIdx.x);
 }
 
+#ifndef DVBM_PART  // non-template kernel: main unit only
 __global__ void k_accumulate2(const double* __restrict__ sums, double* __restrict__ out) {
   if (threadIdx.x == 0) {
     out[0] += sums[0];
     out[1] += sums[1];
   }
 }
+#endif
 
 template <int SPLIT, class S>
 __global__ __launch_bounds__(256) void k_adjoint_readout(const typename S::T* __restrict__ state,
@@ -411,6 +466,7 @@ struct dvbm_handle {
   double* ws;
   hipStream_t stream;
   double dt;
+  mutable int sweep_kseg;  // row ranges per strip of the column-sweep kernel (0: not chosen yet)
 };
 
 namespace {
@@ -442,6 +498,33 @@ KParams make_kparams(const dvbm_params& p, double dt) {
   return k;
 }
 
+// Row ranges per strip group for the column sweep: as many workgroups as
+// the device holds at once (one per strip group and range), but ranges of
+// at least 8 rows so that the 4 warm-up rows of a range stay a minor cost.
+int sweep_ranges(const void* kern, int ngroups, int ny) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 128 * SWEEP_K, 0) != hipSuccess || ncu <= 0 || per_cu <= 0) {
+    (void)hipGetLastError();
+    ncu = 256;
+    per_cu = 1;
+  }
+  const int cap = ncu * per_cu;
+  int want = cap / ngroups < ny / 9 ? cap / ngroups : ny / 9;
+  if (want < 1) want = 1;
+  // the number of ranges of sweep_len rows that cover the column
+  const int len = sweep_len(ny, want);
+  return (ny + len - 1) / len;
+}
+
+}  // namespace
+
+// Step and adjoint launchers: defined here for every translation unit, each
+// split x storage instantiated in one kernel unit (compiled with DVBM_PART,
+// in parallel with the others) and declared extern in the main unit.
+namespace dvbm_launch {
+
 template <int SPLIT, class S, int BCX, int BCY, int PRM>
 void launch_step_pr(const dvbm_handle* h, const void* src, void* dst) {
   using T = typename S::T;
@@ -451,6 +534,14 @@ void launch_step_pr(const dvbm_handle* h, const void* src, void* dst) {
     const dim3 grid(((h->p.nx + TILE_TX - 1) / TILE_TX) * ((h->p.ny + TILE_TY - 1) / TILE_TY));
     hipLaunchKernelGGL((k_collide_advect_lds<SPLIT, S, BCX, BCY, PRM>), grid, dim3(TILE_TX, TILE_TY), 0, h->stream,
                        s, d, h->kp);
+  } else if (DVBM_SWEEP && uint64_t(h->kp.plane) * h->Q * sizeof(T) <= (uint64_t(1) << 31)) {
+    const auto kern = k_collide_advect_sweep<SPLIT, S, BCX, BCY, PRM>;
+    const int nstrips = (h->p.nx + SWEEP_OWN - 1) / SWEEP_OWN;
+    const int ngroups = (nstrips + SWEEP_K - 1) / SWEEP_K;
+    if (h->sweep_kseg == 0) h->sweep_kseg = sweep_ranges(reinterpret_cast<const void*>(kern), ngroups, h->p.ny);
+    const int total = ngroups * h->sweep_kseg;
+    const dim3 grid(8 * ((total + 7) / 8));
+    hipLaunchKernelGGL(kern, grid, dim3(128 * SWEEP_K), 0, h->stream, s, d, h->kp, ngroups, h->sweep_kseg);
   } else {
     const dim3 grid(((h->p.nx + CELL_TX - 1) / CELL_TX) * ((h->p.ny + CELL_TY - 1) / CELL_TY));
     hipLaunchKernelGGL((k_collide_advect<SPLIT, S, BCX, BCY, PRM>), grid, dim3(CELL_TX, CELL_TY), 0, h->stream, s,
@@ -470,7 +561,7 @@ void launch_step_bc(const dvbm_handle* h, const void* src, void* dst) {
 }
 
 template <int SPLIT, class S>
-void launch_step_s(const dvbm_handle* h, const void* src, void* dst) {
+void step(const dvbm_handle* h, const void* src, void* dst) {
   const int bx = h->p.bc_x, by = h->p.bc_y;
   if (bx == DVBM_PERIODIC && by == DVBM_PERIODIC)
     launch_step_bc<SPLIT, S, BC_PERIODIC, BC_PERIODIC>(h, src, dst);
@@ -481,6 +572,74 @@ void launch_step_s(const dvbm_handle* h, const void* src, void* dst) {
   else
     launch_step_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_ZERO_GRADIENT>(h, src, dst);
 }
+
+template <int SPLIT, class S, int BCX, int BCY>
+void adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, double* lam0);
+
+template <int SPLIT, class S>
+void adjoint(const dvbm_handle* h, const void* state, const double* lam1, double* lam0) {
+  const int bx = h->p.bc_x, by = h->p.bc_y;
+  if (bx == DVBM_PERIODIC && by == DVBM_PERIODIC)
+    adjoint_bc<SPLIT, S, BC_PERIODIC, BC_PERIODIC>(h, state, lam1, lam0);
+  else if (bx == DVBM_ZERO_GRADIENT && by == DVBM_PERIODIC)
+    adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_PERIODIC>(h, state, lam1, lam0);
+  else if (bx == DVBM_PERIODIC && by == DVBM_ZERO_GRADIENT)
+    adjoint_bc<SPLIT, S, BC_PERIODIC, BC_ZERO_GRADIENT>(h, state, lam1, lam0);
+  else
+    adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_ZERO_GRADIENT>(h, state, lam1, lam0);
+}
+
+template <int SPLIT, class S, int BCX, int BCY>
+void adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, double* lam0) {
+  using T = typename S::T;
+  const T* s = static_cast<const T*>(state);
+  const double tau = h->p.tau_ref;
+  const dim3 grid(RED_BLOCKS), block(RED_THREADS);
+  switch (pr_mode(h->p.Pr)) {
+    case PR_UNIT:
+      hipLaunchKernelGGL((k_adjoint_step<SPLIT, S, BCX, BCY, PR_UNIT>), grid, block, 0, h->stream, s, lam1, lam0,
+                         h->kp, tau, h->ws);
+      break;
+    case PR_LOW:
+      hipLaunchKernelGGL((k_adjoint_step<SPLIT, S, BCX, BCY, PR_LOW>), grid, block, 0, h->stream, s, lam1, lam0,
+                         h->kp, tau, h->ws);
+      break;
+    default:
+      hipLaunchKernelGGL((k_adjoint_step<SPLIT, S, BCX, BCY, PR_HIGH>), grid, block, 0, h->stream, s, lam1, lam0,
+                         h->kp, tau, h->ws);
+      break;
+  }
+}
+
+}  // namespace dvbm_launch
+
+#if defined(DVBM_PART)
+// kernel unit DVBM_PART = 4 (split - 1) + storage + 1
+template void dvbm_launch::step<(DVBM_PART - 1) / 4 + 1, DVBM_PART_STORE>(const dvbm_handle*, const void*, void*);
+#if (DVBM_PART - 1) % 4 < 2
+template void dvbm_launch::adjoint<(DVBM_PART - 1) / 4 + 1, DVBM_PART_STORE>(const dvbm_handle*, const void*,
+                                                                            const double*, double*);
+#endif
+#else
+#define DVBM_EXTERN_STEP(SPLIT, S) \
+  extern template void dvbm_launch::step<SPLIT, S>(const dvbm_handle*, const void*, void*);
+#define DVBM_EXTERN_ADJ(SPLIT, S)                                                                          \
+  extern template void dvbm_launch::adjoint<SPLIT, S>(const dvbm_handle*, const void*, const double*, \
+                                                      double*);
+DVBM_EXTERN_STEP(1, StoreF64)
+DVBM_EXTERN_STEP(1, StoreF32)
+DVBM_EXTERN_STEP(1, StoreBF16)
+DVBM_EXTERN_STEP(1, StoreF16)
+DVBM_EXTERN_STEP(2, StoreF64)
+DVBM_EXTERN_STEP(2, StoreF32)
+DVBM_EXTERN_STEP(2, StoreBF16)
+DVBM_EXTERN_STEP(2, StoreF16)
+DVBM_EXTERN_ADJ(1, StoreF64)
+DVBM_EXTERN_ADJ(1, StoreF32)
+DVBM_EXTERN_ADJ(2, StoreF64)
+DVBM_EXTERN_ADJ(2, StoreF32)
+
+namespace {
 
 // Calls F<SPLIT, Store>::run(args...) for the handle's split and storage.
 template <template <int, class> class F, class... A>
@@ -504,7 +663,7 @@ void dispatch(const dvbm_params& p, A&&... args) {
 
 template <int SPLIT, class S>
 struct StepOp {
-  static void run(const dvbm_handle* h, const void* src, void* dst) { launch_step_s<SPLIT, S>(h, src, dst); }
+  static void run(const dvbm_handle* h, const void* src, void* dst) { dvbm_launch::step<SPLIT, S>(h, src, dst); }
 };
 
 template <int SPLIT, class S>
@@ -545,40 +704,10 @@ struct EncodeOp {
   }
 };
 
-template <int SPLIT, class S, int BCX, int BCY>
-void launch_adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, double* lam0) {
-  using T = typename S::T;
-  const T* s = static_cast<const T*>(state);
-  const double tau = h->p.tau_ref;
-  const dim3 grid(RED_BLOCKS), block(RED_THREADS);
-  switch (pr_mode(h->p.Pr)) {
-    case PR_UNIT:
-      hipLaunchKernelGGL((k_adjoint_step<SPLIT, S, BCX, BCY, PR_UNIT>), grid, block, 0, h->stream, s, lam1, lam0,
-                         h->kp, tau, h->ws);
-      break;
-    case PR_LOW:
-      hipLaunchKernelGGL((k_adjoint_step<SPLIT, S, BCX, BCY, PR_LOW>), grid, block, 0, h->stream, s, lam1, lam0,
-                         h->kp, tau, h->ws);
-      break;
-    default:
-      hipLaunchKernelGGL((k_adjoint_step<SPLIT, S, BCX, BCY, PR_HIGH>), grid, block, 0, h->stream, s, lam1, lam0,
-                         h->kp, tau, h->ws);
-      break;
-  }
-}
-
 template <int SPLIT, class S>
 struct AdjointOp {
   static void run(const dvbm_handle* h, const void* state, const double* lam1, double* lam0) {
-    const int bx = h->p.bc_x, by = h->p.bc_y;
-    if (bx == DVBM_PERIODIC && by == DVBM_PERIODIC)
-      launch_adjoint_bc<SPLIT, S, BC_PERIODIC, BC_PERIODIC>(h, state, lam1, lam0);
-    else if (bx == DVBM_ZERO_GRADIENT && by == DVBM_PERIODIC)
-      launch_adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_PERIODIC>(h, state, lam1, lam0);
-    else if (bx == DVBM_PERIODIC && by == DVBM_ZERO_GRADIENT)
-      launch_adjoint_bc<SPLIT, S, BC_PERIODIC, BC_ZERO_GRADIENT>(h, state, lam1, lam0);
-    else
-      launch_adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_ZERO_GRADIENT>(h, state, lam1, lam0);
+    dvbm_launch::adjoint<SPLIT, S>(h, state, lam1, lam0);
   }
 };
 
@@ -716,6 +845,7 @@ int dvbm_init(const dvbm_params* p, const double* rho, const double* ux, const d
   h->cur = 0;
   h->ws = ws;
   h->stream = s;
+  h->sweep_kseg = 0;
   dispatch<InitOp>(h->p, h, rho, ux, uy, T, buf0);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -832,3 +962,5 @@ int dvbm_adjoint_init(dvbm_handle* h, const double* lam0, const double* rho, con
 }
 
 }  // extern "C"
+
+#endif  // DVBM_PART

@@ -15,6 +15,7 @@ __device__ inline double g_ref_over_w(const KParams& kp, int i) {
   using L = GH<Set<SPLIT>::N1>;
   constexpr int N1 = Set<SPLIT>::N1;
   const double xa = L::xi(i / N1), xb = L::xi(i % N1);
+  if (SPLIT == 2) return kp.gr0;  // the rest g of split II carries no |xi|^2 term
   return kp.gr0 + kp.gr1 * (xa * xa + xb * xb - 2.0);
 }
 

@@ -1,0 +1,318 @@
+// Column-sweep form of the fused DDF-QE DVBM step for 32-bit and 16-bit
+// storage (float32 arithmetic).
+//
+// A workgroup of two waves owns a strip of SWEEP_OWN columns and walks a
+// range of rows in +y; one wave advances f, the other g.  The 64 lanes of a
+// wave hold the columns x0 - 2 .. x0 + 61: lanes 2 .. 61 own their cells,
+// the two lanes at each end only supply the x stencil of their neighbours.  The x neighbours of a population come from the adjacent lanes
+// (DPP wave shifts), the y neighbours from a window of rows kept in registers
+// per population plane, so every stored value is read from memory once per
+// strip (the 4 overlap columns and the 4 warm-up rows of a range aside).
+// While a row is being finished, each plane's next row is already in flight.
+#pragma once
+
+#include "step.h"
+
+namespace dvbm {
+
+constexpr int SWEEP_OWN = 60;  // cells per strip: 64 lanes minus 2 stencil lanes on each side
+
+// A loaded value kept in a float32 register as its stored bit pattern (the
+// 16-bit formats zero-extended), so that the decode, and with it the wait for
+// the load, happens at the value's first use rather than right after the load.
+template <class T>
+struct Bits;
+template <>
+struct Bits<float> {
+  __device__ static float keep(float v) { return v; }
+  __device__ static float decode(float b) { return b; }
+};
+template <>
+struct Bits<uint16_t> {  // bfloat16: the high half of a float32
+  __device__ static float keep(uint16_t v) { return __builtin_bit_cast(float, uint32_t(v)); }
+  __device__ static float decode(float b) { return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, b) << 16); }
+};
+template <>
+struct Bits<_Float16> {
+  __device__ static float keep(_Float16 v) { return __builtin_bit_cast(float, uint32_t(__builtin_bit_cast(uint16_t, v))); }
+  __device__ static float decode(float b) {
+    return float(__builtin_bit_cast(_Float16, uint16_t(__builtin_bit_cast(uint32_t, b))));
+  }
+};
+
+// Value held by lane l - 1 (l + 1) of the wave; lane 0 (63) reads 0.
+__device__ inline float lane_prev(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
+}
+__device__ inline float lane_next(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+}
+
+// Float64 moments (Eqs. eq_quadratur1-3, Table I notation) of one
+// distribution, accumulated one pair of +-xi_a columns at a time: the ten
+// moments of orders 0-3 of f (D = 0) or the three of orders 0-1 of g (D = 1).
+template <int D, int N1, class R>
+__device__ inline void half_moments(const R* v, double* out) {
+  using L = GH<N1>;
+  constexpr int NM = D == 0 ? 10 : 3;
+  double acc[NM];
+  double u1, u2, u3;
+  if (L::has_zero) {
+    constexpr int a = N1 / 2;
+    double s0, s1, s2, s3;
+    pair_sums<N1>(v + a * N1, s0, s1, s2, s3);
+    if (D == 0) {
+      // rho, jx, jy, pxx, pxy, pyy, qxxx, qxxy, qxyy, qyyy
+      acc[0] = s0; acc[1] = 0.0; acc[2] = s1; acc[3] = 0.0; acc[4] = 0.0;
+      acc[5] = s2; acc[6] = 0.0; acc[7] = 0.0; acc[8] = 0.0; acc[9] = s3;
+    } else {
+      // g0, qgx, qgy
+      acc[0] = s0; acc[1] = 0.0; acc[2] = s1;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NM; ++k) acc[k] = 0.0;
+  }
+  (void)u1; (void)u2; (void)u3;
+#pragma unroll
+  for (int k = 0; k < N1 / 2; ++k) {
+    const int pa = N1 - 1 - k;
+    const double x = L::xi(pa);
+    double a0, a1, a2, a3, b0, b1, b2, b3;
+    pair_sums<N1>(v + pa * N1, a0, a1, a2, a3);
+    pair_sums<N1>(v + k * N1, b0, b1, b2, b3);
+    const double e0 = a0 + b0, o0 = a0 - b0, e1 = a1 + b1;
+    if (D == 0) {
+      const double o1 = a1 - b1, e2 = a2 + b2, o2 = a2 - b2;
+      acc[0] += e0;
+      acc[1] += x * o0;
+      acc[2] += e1;
+      acc[3] += (x * x) * e0;
+      acc[4] += x * o1;
+      acc[5] += e2;
+      acc[6] += (x * x * x) * o0;
+      acc[7] += (x * x) * e1;
+      acc[8] += x * o2;
+      acc[9] += a3 + b3;
+    } else {
+      acc[0] += e0;
+      acc[1] += x * o0;
+      acc[2] += e1;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NM; ++k) out[k] = acc[k];
+}
+
+// Moment exchange between the two waves of a strip: 13 float64 moments per
+// lane, double-buffered by row parity so one barrier per row suffices.
+struct SweepShared {
+  double m[2][N_MOMENTS][64];
+};
+
+// Strips per workgroup: the 2 SWEEP_K waves of a workgroup advance SWEEP_K
+// adjacent strips in lock-step (one barrier per row), so that each plane row
+// is read and written as one contiguous span and the overlap columns of
+// neighbouring strips are shared through the caches.
+#ifndef DVBM_SWEEP_K
+#define DVBM_SWEEP_K 4
+#endif
+constexpr int SWEEP_K = DVBM_SWEEP_K;
+
+// Rows [ya, yb) of the strip whose first owned column is x0, distribution D
+// (0: f, 1: g); yb - ya is a positive multiple of 3.  The other
+// distribution of the strip is advanced by the other wave of the workgroup,
+// which shares the moments through sh.
+//
+// Each face value of the NND reconstruction is formed once and used by the
+// two cells that share the face: in x the upwind cell's lane forms it and
+// its neighbour reads it by a lane shift; in y the value of the face below
+// row y is carried over from row y - 1.  Window of plane i (y-node xi_b):
+// rows y-1 .. y+1 when xi_b > 0, y .. y+2 when xi_b < 0 (upwind side
+// first), rows y .. y+2 when xi_b = 0 (loaded early, since the row's
+// moments need it first).  A window of three rows lives in three registers
+// whose roles rotate from row to row, so the row loop is unrolled three
+// times and a row's load lands directly in the register that the window
+// drops.
+template <int SPLIT, class S, int BCX, int BCY, int PRM, int D>
+__device__ inline void sweep_update(const typename S::T* __restrict__ src, typename S::T* __restrict__ dst,
+                                    const KParams& kp, int x0, int ya, int yb, SweepShared& sh) {
+  using R = typename S::C;
+  using T = typename S::T;
+  static_assert(sizeof(R) == 4, "the sweep computes in float32");
+  constexpr int N1 = Set<SPLIT>::N1;
+  constexpr int Q = Set<SPLIT>::Q;
+  constexpr int N = D == 0 ? Set<SPLIT>::NF : 2;  // Grad order of this distribution
+  constexpr uint32_t SZ = sizeof(T);
+  using L = GH<N1>;
+
+  const int lane = threadIdx.x & 63;
+  const int x = x0 - 2 + lane;
+  const bool own = lane >= 2 && lane < 62 && x < kp.nx;
+  const uint32_t vo = uint32_t(wrap_any<BCX>(x, kp.nx)) * SZ;
+  // stores of the stencil-only lanes go to offset 2^31, which the bounds
+  // check of the buffer resource (a distribution of at most 2^31 bytes)
+  // discards: every lane stores, so no branch splits the memory counters
+  const uint32_t vo_st = own ? vo : 0x80000000u;
+  const uint32_t row_bytes = uint32_t(kp.pitch) * SZ;
+  const uint32_t plane_bytes = uint32_t(kp.plane) * SZ;
+  const uint32_t dist_bytes = plane_bytes * uint32_t(Q);
+  const rsrc_t rsrc_src = dist_rsrc(src, D, dist_bytes);
+  const rsrc_t rsrc_dst = dist_rsrc(dst, D, dist_bytes);
+  const int ny = kp.ny;
+  const R beta2 = R(kp.beta2);
+  const R kx = R(kp.kx), ky = R(kp.ky);
+  auto row = [&](int yy) -> uint32_t { return uint32_t(wrap<BCY>(yy, ny)) * row_bytes; };
+  // stored bit pattern of plane i at row offset roff; Bits<T>::decode gives the stored value
+  auto load = [&](int i, uint32_t roff) -> R {
+    return Bits<T>::keep(Buf<T>::ld(rsrc_src, uint32_t(i) * plane_bytes + roff, vo));
+  };
+  // face value between c and n, upwind cell c, far-side cell u: c + L(c - u, n - c) / 4
+  auto face = [&](R u, R c, R n) -> R { return c + R(0.25) * lim4(c - u, n - c, beta2); };
+  auto rest = [&](int i) -> R { return R(D == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i)); };
+
+  // win[i][(P + r) % 3] holds window row r at phase P = (y - ya) % 3; a
+  // row enters the window as its bit pattern and is decoded in place at its
+  // first use (y-moving planes: the face above the row two rows earlier;
+  // xi_b = 0: as the row's own value)
+  R win[Q][3];
+  R fbelow[Q];  // face value below the current row (planes with xi_b != 0)
+  {
+    // warm-up, issued in the order of first use: rows y-2 .. y, then the
+    // lead rows of the planes with xi_b < 0 (their groups come first), of
+    // xi_b > 0, and the two rows of xi_b = 0 needed from the next row on
+    R extra[Q];
+    constexpr int order[7][2] = {{-2, 0}, {-1, 0}, {0, 0}, {1, -1}, {2, -1}, {1, 1}, {1, 2}};
+#pragma unroll
+    for (int s = 0; s < 7; ++s) {
+      const int dy = order[s][0], side = order[s][1];  // side: sign of xi_b that loads (0: all)
+      const uint32_t ro = row(ya + dy);
+      static_for<Q>([&](auto kc) {
+        constexpr int i = decltype(kc)::value;
+        constexpr double xb = L::xi(i % N1);
+        if (side == 2) {
+          if (xb == 0.0) win[i][2] = load(i, row(ya + 2));
+          return;
+        }
+        if (side != 0 && !((side > 0 && xb > 0.0) || (side < 0 && xb <= 0.0))) return;
+        if (xb > 0.0) {
+          if (dy == -2) extra[i] = load(i, ro);
+          else if (dy <= 1) win[i][dy + 1] = load(i, ro);
+        } else if (xb < 0.0) {
+          if (dy == -1) extra[i] = load(i, ro);
+          else if (dy >= 0) win[i][dy] = load(i, ro);
+        } else if (dy >= 0 && dy <= 1) {
+          win[i][dy] = load(i, ro);
+        }
+      });
+    }
+    static_for<Q>([&](auto kc) {
+      constexpr int i = decltype(kc)::value;
+      constexpr double xb = L::xi(i % N1);
+      if (xb != 0.0) {
+        // window row 2 is decoded by the first row step, at its first use
+        win[i][0] = Bits<T>::decode(win[i][0]);
+        win[i][1] = Bits<T>::decode(win[i][1]);
+        const R e = Bits<T>::decode(extra[i]);
+        fbelow[i] = xb > 0.0 ? face(e, win[i][0], win[i][1]) : face(win[i][1], win[i][0], e);
+      }
+    });
+  }
+
+  auto row_step = [&](auto phc, int y) {
+    constexpr int P = decltype(phc)::value;
+    const uint32_t r_st = uint32_t(y) * row_bytes;
+    const uint32_t r_p2 = row(y + 2), r_p3 = row(y + 3);
+
+    // the row's populations (stored values), their float64 moments, shared
+    R cen[Q];
+    static_for<Q>([&](auto kc) {
+      constexpr int i = decltype(kc)::value;
+      constexpr double xb = L::xi(i % N1);
+      if (xb == 0.0) win[i][P] = Bits<T>::decode(win[i][P]);
+      cen[i] = xb > 0.0 ? win[i][(P + 1) % 3] : win[i][P];
+    });
+    NodeMoments m;
+    {
+      R v[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) v[i] = S::dev ? R(weight<SPLIT>(i)) * (rest(i) + cen[i]) : cen[i];
+      double part[D == 0 ? 10 : 3];
+      half_moments<D, N1>(v, part);
+      double(*xm)[64] = sh.m[y & 1];
+#pragma unroll
+      for (int k = 0; k < (D == 0 ? 10 : 3); ++k) xm[(D == 0 ? 0 : 10) + k][lane] = part[k];
+      __syncthreads();
+      m.rho = xm[0][lane]; m.jx = xm[1][lane]; m.jy = xm[2][lane];
+      m.pxx = xm[3][lane]; m.pxy = xm[4][lane]; m.pyy = xm[5][lane];
+      m.qxxx = xm[6][lane]; m.qxxy = xm[7][lane]; m.qxyy = xm[8][lane]; m.qyyy = xm[9][lane];
+      m.g0 = xm[10][lane]; m.qgx = xm[11][lane]; m.qgy = xm[12][lane];
+    }
+    R bf[5][5], bg[3][3], om1;
+    collision_coeffs<SPLIT, PRM, R>(m, kp, kp.om_scale, kp.Pr, bf, bg, om1);
+    const R keep = R(1) - om1;
+
+    // groups of the N1 populations i = a N1 + b that share the y-node b
+    static_for<N1>([&](auto gc) {
+      constexpr int ybn = decltype(gc)::value;
+      constexpr double xb = L::xi(ybn);
+      R c[5];
+#pragma unroll
+      for (int p = 0; p <= 4; ++p) {
+        c[p] = R(0);
+        if (p > N) continue;
+#pragma unroll
+        for (int q = 0; p + q <= N; ++q) {
+          const double h = hn(q, xb);
+          if (h != 0.0) c[p] += (D == 0 ? bf[p][q] : bg[p][q]) * R(h);
+        }
+      }
+      static_for<N1>([&](auto ac) {
+        constexpr int xa = decltype(ac)::value;
+        constexpr int i = xa * N1 + ybn;
+        constexpr double xv = L::xi(xa);
+        constexpr double w = GH<N1>::w(xa) * GH<N1>::w(ybn);
+        R* wn = win[i];
+        const R c0 = cen[i];
+        const R rr = S::dev ? rest(i) : R(0);
+        const R X = S::dev ? R(w) * (rr + c0) : c0;
+        // collision: (1 - om1) X + w_i sum_p He_p(xi_a)/p! c_p
+        R xn = keep * X;
+#pragma unroll
+        for (int p = 0; p <= 4; ++p) {
+          if (p > N) continue;
+          const double h = hn(p, xv);
+          if (h != 0.0) xn += R(w * h) * c[p];
+        }
+        // advection: -(dt/dx) v_x (X_{x+1/2} - X_{x-1/2}) - (dt/dy) v_y (X_{y+1/2} - X_{y-1/2})
+        R div = R(0);
+        if (xv > 0.0) {
+          const R fr = face(lane_prev(c0), c0, lane_next(c0));  // X_{x+1/2}
+          div += kx * R(xv) * (fr - lane_prev(fr));
+        } else if (xv < 0.0) {
+          const R fl = face(lane_next(c0), c0, lane_prev(c0));  // X_{x-1/2}
+          div += kx * R(xv) * (lane_next(fl) - fl);
+        }
+        if (xb != 0.0) {
+          wn[(P + 2) % 3] = Bits<T>::decode(wn[(P + 2) % 3]);
+          const R r0 = wn[P], r1 = wn[(P + 1) % 3], r2 = wn[(P + 2) % 3];
+          const R fa = xb > 0.0 ? face(r0, r1, r2) : face(r2, r1, r0);  // X_{y+1/2}
+          div += ky * R(xb) * (fa - fbelow[i]);
+          fbelow[i] = fa;
+        }
+        xn -= S::dev ? R(w) * div : div;
+        Buf<T>::st(rsrc_dst, uint32_t(i) * plane_bytes + r_st, vo_st, S::enc(xn, R(1.0 / w), rr));
+        // the window drops its first row; that register receives the row it now needs
+        wn[P] = load(i, xb > 0.0 ? r_p2 : r_p3);
+      });
+    });
+  };
+
+  for (int y = ya; y < yb; y += 3) {
+    row_step(std::integral_constant<int, 0>{}, y);
+    row_step(std::integral_constant<int, 1>{}, y + 1);
+    row_step(std::integral_constant<int, 2>{}, y + 2);
+  }
+}
+
+}  // namespace dvbm
