@@ -74,6 +74,125 @@ def traffic_entry(kernel_key: str):
     return ent["fetch_bytes"] * data["copy_scale_fetch"] + ent["write_bytes"] * data["copy_scale_write"]
 
 
+def step_kernel_name(storage: str, wl) -> str:
+    """The step kernel the library launches for this storage and grid size."""
+    if storage == "f64":
+        return "k_collide_advect_lds"
+    pitch = (wl.nx + 63) // 64 * 64
+    Q = 25
+    if wl.nx * wl.ny >= 3 << 18 and pitch * wl.ny * Q * STORAGE_BYTES[storage] <= 1 << 31:
+        return "k_collide_advect_sweep"
+    return "k_collide_advect"
+
+
+# rocprofv3 commands whose outputs write_profiles() summarises (run from the repository root on the GPU)
+PROFILE_COMMANDS = {
+    "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_trace -o trace -- "
+             "python bench.py",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_fetch -o pmc -- "
+             "python bench.py --steps 20 --warmup 2 --modes none --no-adjoint --no-cpu-baseline",
+    "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_write -o pmc -- "
+             "python bench.py --steps 20 --warmup 2 --modes none --no-adjoint --no-cpu-baseline",
+}
+
+
+def write_profiles(trace_dir: str, fetch_csv: str, write_csv: str, bench_json: str, workload: str,
+                   storage: str) -> None:
+    """Summaries of the three PROFILE_COMMANDS runs under profiles/ (host only, no GPU).
+
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are calibrated against the
+    plain device copies that bench.py runs (copy_bandwidth: 4 GiB read + 4 GiB
+    written per dispatch): scale = known bytes / counter bytes.
+    """
+    import csv
+    import statistics
+
+    with open(bench_json) as fh:
+        line = json.loads([ln for ln in fh if ln.startswith("{")][-1])
+    kname = line["roofline"]["kernel"]
+
+    def per_kernel(path, counter):
+        vals, copies = [], []
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                v = float(r["Counter_Value"]) * 1024.0
+                if kname + "<" in r["Kernel_Name"]:
+                    vals.append(v)
+                elif "copy" in r["Kernel_Name"].lower():
+                    copies.append(v)
+        big = [v for v in copies if v >= 0.5 * max(copies)]  # the 4 GiB copies of copy_bandwidth()
+        return statistics.median(vals), statistics.median(big), len(vals), len(big)
+
+    fetch, fcopy, nf, ncf = per_kernel(fetch_csv, "FETCH_SIZE")
+    write, wcopy, nw, ncw = per_kernel(write_csv, "WRITE_SIZE")
+    copy_bytes = float(4 << 30)
+    sf, sw = copy_bytes / fcopy, copy_bytes / wcopy
+    cells = line["config"]["nx"] * line["config"]["ny"]
+    alg = line["roofline"]["bytes_per_update"] * cells
+    with open(os.path.join(trace_dir, "trace_kernel_stats.csv")) as fh:
+        stats = list(csv.DictReader(fh))
+    # per-dispatch durations of the step kernel at the bench workload's grid (the largest grid it was
+    # launched with: the adjoint measurement launches the same kernel on a small grid)
+    store = {"f64": "StoreF64", "f32": "StoreF32", "bf16_dev": "StoreBF16", "fp16_dev": "StoreF16"}[storage]
+    inst = f"{kname}<{line['config']['split']}, dvbm::{store},"
+    durs = {}
+    with open(os.path.join(trace_dir, "trace_kernel_trace.csv")) as fh:
+        for r in csv.DictReader(fh):
+            if inst in r["Kernel_Name"]:
+                g = int(r["Grid_Size_X"])
+                durs.setdefault(g, []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    gmax = max(durs)
+    avg_ns = sum(durs[gmax]) / len(durs[gmax])
+    key = f"collide_advect/{workload}/{storage}"
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    data = {}
+    if os.path.exists(tpath):
+        with open(tpath) as fh:
+            data = json.load(fh)
+    if data.get("source_hash") != source_hash():
+        data = {"kernels": {}}
+    data.update({"source_hash": source_hash(), "copy_scale_fetch": sf, "copy_scale_write": sw})
+    data["kernels"][key] = {"fetch_bytes": fetch, "write_bytes": write, "kernel": kname}
+    with open(tpath, "w") as fh:
+        json.dump(data, fh, indent=1)
+        fh.write("\n")
+    name = f"{kname}_{workload}_{storage}"
+    rows = sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:8]
+    with open(os.path.join(ROOT, "profiles", f"{name}_kernel_trace.md"), "w") as fh:
+        fh.write(f"# {kname}: kernel trace, {workload}, {storage} storage\n\n")
+        fh.write(f"Command (repository root, one MI355X):\n\n    {PROFILE_COMMANDS['trace']}\n\n")
+        fh.write("| kernel | calls | average ns | total ns |\n|---|---|---|---|\n")
+        for r in rows:
+            fh.write(f"| `{r['Name'][:110]}` | {r['Calls']} | {float(r['AverageNs']):.0f} | {r['TotalDurationNs']} |\n")
+        ms_ev = line["ms_per_step"]
+        fh.write(f"\nThe table averages every launch of a kernel instance (the adjoint measurement also launches "
+                 f"the step kernel on its 256 x 256 grid). The {len(durs[gmax])} launches of {kname} on the "
+                 f"{line['config']['nx']} x {line['config']['ny']} grid ({gmax} threads) average {avg_ns:.0f} ns; "
+                 f"the bench line of the same run times it at {ms_ev * 1e6:.0f} ns per launch with HIP events "
+                 f"on the solver stream ("
+                 f"{100 * (avg_ns / (ms_ev * 1e6) - 1):+.2f} %). Algorithmic bytes per launch "
+                 f"{alg / 1e9:.3f} GB -> {alg / avg_ns:.0f} GB/s by the trace average, "
+                 f"{line['roofline']['achieved']} GB/s by the events.\n")
+    with open(os.path.join(ROOT, "profiles", f"{name}_hbm_traffic.md"), "w") as fh:
+        fh.write(f"# {kname}: HBM traffic, {workload}, {storage} storage\n\n")
+        fh.write("Commands (repository root, one MI355X):\n\n")
+        fh.write(f"    {PROFILE_COMMANDS['fetch']}\n    {PROFILE_COMMANDS['write']}\n\n")
+        fh.write("| counter | kernel, per dispatch (median) | copy calibration | scaled bytes | algorithmic |\n")
+        fh.write("|---|---|---|---|---|\n")
+        fh.write(f"| FETCH_SIZE | {fetch / 1024:.0f} KiB ({nf} dispatches) | 4 GiB copy reads {fcopy / 1024:.0f} KiB "
+                 f"-> x{sf:.3f} | {fetch * sf / 1e9:.3f} GB | {alg / 2e9:.3f} GB read |\n")
+        fh.write(f"| WRITE_SIZE | {write / 1024:.0f} KiB ({nw} dispatches) | 4 GiB copy writes {wcopy / 1024:.0f} KiB "
+                 f"-> x{sw:.3f} | {write * sw / 1e9:.3f} GB | {alg / 2e9:.3f} GB written |\n")
+        tot = fetch * sf + write * sw
+        fh.write(f"\nMeasured traffic per launch {tot / 1e9:.3f} GB = {tot / alg:.3f} x the algorithmic "
+                 f"{alg / 1e9:.3f} GB (one read and one write of the 2Q populations of every cell).\n")
+    print(f"profiles written for {key}: trace {avg_ns:.0f} ns, traffic {tot / 1e9:.3f} GB "
+          f"(fetch x{sf:.3f}, write x{sw:.3f})")
+
+
 def time_mode(wl, phys, storage, steps, warmup, device):
     import torch
 
@@ -204,7 +323,7 @@ def copy_bandwidth(device, nbytes=4 << 30, reps=5):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(n=512, steps=40):
+def cpu_baseline(n=256, steps=200):
     """The FP64 oracle on the host: same workload family on an n x n sample."""
     import numpy as np
     import torch
@@ -235,9 +354,13 @@ def main():
                     help="extra storages timed after the main one ('none' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 1 GiB device copy (reference for HBM counter scaling)")
+    ap.add_argument("--write-profiles", nargs=4, metavar=("TRACE_DIR", "FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
+                    help="host only: summarise the rocprofv3 runs of PROFILE_COMMANDS into profiles/")
     args = ap.parse_args()
+
+    if args.write_profiles:
+        write_profiles(*args.write_profiles, workload=args.workload, storage=args.storage)
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs (domain decomposition with "
@@ -275,18 +398,12 @@ def main():
         print("[bench] adjoint cost on the 256x256 gradient workload", file=sys.stderr, flush=True)
         adjoint = adjoint_cost(device)
     copy_gbps = copy_bandwidth(device)
-    if args.copy_calibration:
-        a = torch.empty(1 << 30, dtype=torch.uint8, device=device)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
 
     kernel_key = f"collide_advect/{args.workload}/{args.storage}"
     traffic = traffic_entry(kernel_key)
     roofline = {"bound": "hbm", "achieved": round(main["GBps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(main["frac"], 4), "traffic": traffic,
-                "bytes_per_update": main["bytes_per_update"], "kernel": "k_collide_advect",
+                "bytes_per_update": main["bytes_per_update"], "kernel": step_kernel_name(args.storage, wl),
                 "copy_kernel_GBps": round(copy_gbps, 1)}
     cpu = None
     if not args.no_cpu_baseline:

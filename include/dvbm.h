@@ -62,10 +62,16 @@ extern "C" {
 enum dvbm_storage { DVBM_F64 = 0, DVBM_F32 = 1, DVBM_BF16_DEV = 2, DVBM_FP16_DEV = 3 };
 enum dvbm_bc { DVBM_PERIODIC = 0, DVBM_ZERO_GRADIENT = 1 };
 enum dvbm_visc { DVBM_CONST_MU = 0, DVBM_CONST_TAU = 1 };
+/* Step kernel (all compute the same update; the choice only affects speed):
+ * AUTO picks the LDS tile kernel for DVBM_F64 and, for the other storages,
+ * the column sweep on grids of at least 3 * 2^18 cells whose distribution
+ * fits 2 GiB, else the per-cell kernel.  SWEEP requires 32/16-bit storage
+ * and a distribution of at most 2 GiB. */
+enum dvbm_kernel { DVBM_KERNEL_AUTO = 0, DVBM_KERNEL_CELL = 1, DVBM_KERNEL_SWEEP = 2, DVBM_KERNEL_TILE = 3 };
 
 /*
  * Simulation parameters (Sec. III A 3).  dvbm_params_default() fills the
- * paper's defaults: split II, F32, periodic, CONST_MU, R = 1, gamma = 1.4,
+ * paper's defaults: split II, F32, periodic, CONST_MU, AUTO kernel, R = 1, gamma = 1.4,
  * Pr = 0.71, mu = 5e-5 (tau_ref = 5e-5 with p_ref = 1), T_ref = 1,
  * beta = 1.2, CFL = 0.01, dt = 0 (CFL rule).
  *
@@ -80,7 +86,7 @@ typedef struct dvbm_params {
   int32_t storage;     /* enum dvbm_storage */
   int32_t bc_x, bc_y;  /* enum dvbm_bc; zero-gradient copies the nearest interior cell into 2 ghost layers */
   int32_t visc_mode;   /* enum dvbm_visc */
-  int32_t reserved;    /* must be 0 */
+  int32_t kernel;      /* enum dvbm_kernel (0 = AUTO) */
   double dx, dy;       /* cell sizes, > 0 */
   double R, gamma;     /* gas constant > 0; 1 < gamma <= 2 (split II needs Cv >= D R / 2) */
   double Pr;           /* Prandtl number > 0 */
@@ -172,14 +178,21 @@ int dvbm_set_state_index(dvbm_handle* h, int index);
  */
 size_t dvbm_adjoint_bytes(const dvbm_params* p);
 
+/* Bytes of the device work array of dvbm_adjoint_step (14 float64 values per
+ * cell: the cotangents of the 13 node moments and 1 - dt/tau_1); 0 if the
+ * parameters are invalid. */
+size_t dvbm_adjoint_work_bytes(const dvbm_params* p);
+
 /* lam_n = (dX_{n+1}/dX_n)^T lam_np1 for the step that maps state_n (a device
  * buffer in the population layout above, e.g. a checkpoint copy) to
  * X_{n+1}.  When dparams != NULL (device double[2]) it is incremented by
  * (dX_{n+1}/dtau_ref)^T lam_np1 and (dX_{n+1}/dPr)^T lam_np1 (at Pr == 1,
- * where Table I has no quasi-equilibrium, the Pr entry is 0).  lam_np1 and
- * lam_n must not overlap.  Asynchronous. */
+ * where Table I has no quasi-equilibrium, the Pr entry is 0).  work is a
+ * caller-owned device array of dvbm_adjoint_work_bytes() bytes (contents
+ * overwritten; calls that share it must not overlap).  lam_np1 and lam_n
+ * must not overlap.  Asynchronous. */
 int dvbm_adjoint_step(dvbm_handle* h, const void* state_n, const double* lam_np1, double* lam_n,
-                      double* dparams);
+                      double* dparams, void* work);
 
 /* lam = sum of (d field / dX)^T d_field over the macroscopic fields of state
  * (rho, u_x, u_y, T of Eqs. eq_quadratur1-3); any d_* may be NULL (zero).

@@ -6,6 +6,7 @@
 
 from .dvbm import (  # noqa: F401
     BC,
+    KERNEL,
     STORAGE,
     VISC,
     DVBMError,

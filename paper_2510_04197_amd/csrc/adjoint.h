@@ -8,8 +8,8 @@
 //  * Relaxation part (local to the cell): F_i = (1 - om1) X_i + w_i sum_k b_k H_k(i).
 //    With mu_k = sum_i lam'_i w_i H_k(i) and s = sum_i lam'_i X_i, the
 //    cotangent of the moment vector m is  mbar_r = sum_k mu_k db_k/dm_r - s dom1/dm_r,
-//    evaluated by forward-mode dual numbers (one pass per moment / parameter)
-//    through the same coefficient code the step kernels use.  Moments are
+//    evaluated by forward-mode dual numbers (ADJ_DIRS seed directions per
+//    pass) through the same coefficient code the step kernels use.  Moments are
 //    linear in X, so lam_j = (1 - om1) lam'_j + sum_r mbar_r dm_r/dX_j.
 //  * Flux part: every face value X_{f-1/2} of the NND reconstruction depends
 //    on three neighbours; the limiter is differentiated on the branch the
@@ -45,6 +45,94 @@ __device__ inline D1 operator/(D1 a, double b) { return D1(a.v / b, a.d / b); }
 __device__ inline D1& operator+=(D1& a, D1 b) { return a = a + b; }
 __device__ inline D1& operator-=(D1& a, D1 b) { return a = a - b; }
 __device__ inline D1& operator*=(D1& a, D1 b) { return a = a * b; }
+
+// Value and N directional derivatives: one pass of the coefficient code
+// carries N seed directions, so the value part is evaluated once per N.
+template <int N>
+struct DN {
+  double v, d[N];
+  __device__ DN() : v(0.0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) d[k] = 0.0;
+  }
+  __device__ DN(double x) : v(x) {  // NOLINT: implicit constant
+#pragma unroll
+    for (int k = 0; k < N; ++k) d[k] = 0.0;
+  }
+};
+template <int N>
+__device__ inline DN<N> operator+(const DN<N>& a, const DN<N>& b) {
+  DN<N> r(a.v + b.v);
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] + b.d[k];
+  return r;
+}
+template <int N>
+__device__ inline DN<N> operator-(const DN<N>& a, const DN<N>& b) {
+  DN<N> r(a.v - b.v);
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] - b.d[k];
+  return r;
+}
+template <int N>
+__device__ inline DN<N> operator-(const DN<N>& a) {
+  DN<N> r(-a.v);
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = -a.d[k];
+  return r;
+}
+template <int N>
+__device__ inline DN<N> operator*(const DN<N>& a, const DN<N>& b) {
+  DN<N> r(a.v * b.v);
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  return r;
+}
+template <int N>
+__device__ inline DN<N> operator/(const DN<N>& a, const DN<N>& b) {
+  const double inv = 1.0 / b.v;
+  DN<N> r(a.v * inv);
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * inv;
+  return r;
+}
+template <int N>
+__device__ inline DN<N> operator+(const DN<N>& a, double b) {
+  DN<N> r = a;
+  r.v += b;
+  return r;
+}
+template <int N>
+__device__ inline DN<N> operator+(double a, const DN<N>& b) { return b + a; }
+template <int N>
+__device__ inline DN<N> operator-(const DN<N>& a, double b) { return a + (-b); }
+template <int N>
+__device__ inline DN<N> operator-(double a, const DN<N>& b) { return (-b) + a; }
+template <int N>
+__device__ inline DN<N> operator*(const DN<N>& a, double b) {
+  DN<N> r(a.v * b);
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b;
+  return r;
+}
+template <int N>
+__device__ inline DN<N> operator*(double a, const DN<N>& b) { return b * a; }
+template <int N>
+__device__ inline DN<N> operator/(const DN<N>& a, double b) { return a * (1.0 / b); }
+template <int N>
+__device__ inline DN<N> operator/(double a, const DN<N>& b) {
+  const double inv = 1.0 / b.v;
+  DN<N> r(a * inv);
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = -r.v * b.d[k] * inv;
+  return r;
+}
+template <int N>
+__device__ inline DN<N>& operator+=(DN<N>& a, const DN<N>& b) { return a = a + b; }
+template <int N>
+__device__ inline DN<N>& operator-=(DN<N>& a, const DN<N>& b) { return a = a - b; }
+template <int N>
+__device__ inline DN<N>& operator*=(DN<N>& a, const DN<N>& b) { return a = a * b; }
 
 // ------------------------------------------------------------ equilibrium of macroscopic fields
 // Grad-Hermite equilibria f^eq, g^eq (Sec. II D 2, App. A, App. D) of one
@@ -146,119 +234,163 @@ __device__ inline double flux_adjoint(const double* Xs, const double* lam, int c
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
       const int q = c + q0 + s;
-      if (wrap_any<BC>(q, n) == c) acc += gface * ps[s];
+      if (wrap<BC>(q, n) == c) acc += gface * ps[s];
     }
   }
   return acc;
 }
 
-// ------------------------------------------------------------ one cell of the adjoint step
-template <int SPLIT, class S, int BCX, int BCY, int PRM>
-__device__ inline void cell_adjoint(const typename S::T* __restrict__ state, const double* __restrict__ lam1,
-                                    double* __restrict__ lam0, const KParams& kp, int x, int y, double tau_ref,
-                                    double& g_tau, double& g_pr) {
-  using T = typename S::T;
+// ------------------------------------------------------------ adjoint step in two kernels
+// The relaxation part needs the 13 + 2 directional derivatives of the
+// coefficient map at every cell; the flux part needs, for every population
+// plane, the plane's stencil.  They run as two kernels:
+//   relax: one thread per (cell, group of ADJ_DIRS directions) writes
+//          mbar_r for its directions and 1 - om1 into a work array
+//          work[r][cell] (r = 0..12 moments, 13: 1 - om1) and accumulates its
+//          share of d/dtau_ref, d/dPr;
+//   flux:  one thread per (population plane, cell) assembles
+//          lam(c) = (1 - om1) lam'(c) + sum_r mbar_r dm_r/dX + flux cotangent.
+constexpr int ADJ_DIRS = 5;                                       // directions per pass
+constexpr int ADJ_GROUPS = (N_MOMENTS + 2 + ADJ_DIRS - 1) / ADJ_DIRS;  // passes per cell
+constexpr int ADJ_WORK_ROWS = N_MOMENTS + 1;
+
+// Stored value of population (d, i) at (x, y), decoded to float64.
+template <int SPLIT, class S>
+__device__ inline double adj_X(const typename S::T* __restrict__ state, const KParams& kp, int d, int i, int y,
+                               int x) {
+  constexpr int Q = Set<SPLIT>::Q;
+  const typename S::T v = state[int64_t(d * Q + i) * kp.plane + int64_t(y) * kp.pitch + x];
+  if (!S::dev) return double(S::raw(v));
+  const double r = d == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i);
+  return weight<SPLIT>(i) * (r + double(S::raw(v)));
+}
+
+template <int SPLIT, class S, int PRM>
+__device__ inline void cell_adjoint_relax(const typename S::T* __restrict__ state, const double* __restrict__ lam1,
+                                          double* __restrict__ work, const KParams& kp, int c, int grp,
+                                          double tau_ref, double& g_tau, double& g_pr) {
   constexpr int N1 = Set<SPLIT>::N1;
   constexpr int Q = Set<SPLIT>::Q;
   constexpr int NF = Set<SPLIT>::NF;
   using L = GH<N1>;
-  const int64_t pitch = kp.pitch, plane = kp.plane;
   const int64_t cells = int64_t(kp.nx) * kp.ny;
+  const int y = c / kp.nx, x = c - y * kp.nx;
 
-  auto X_at = [&](int d, int i, int yy, int xx) -> double {
-    const T v = state[int64_t(d * Q + i) * plane + int64_t(yy) * pitch + xx];
-    if (!S::dev) return double(S::raw(v));
-    const double w = weight<SPLIT>(i);
-    const double r = d == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i);
-    return w * (r + double(S::raw(v)));
-  };
-  auto lam_at = [&](int d, int i, int yy, int xx) -> double {
-    return lam1[int64_t(d * Q + i) * cells + int64_t(yy) * kp.nx + xx];
-  };
-
-  // relaxation part
-  double f[Q], g[Q], lf[Q], lg[Q];
+  // moments of the cell and the lam'-weighted Hermite projections
+  double f[Q], g[Q];
+#pragma unroll
   for (int i = 0; i < Q; ++i) {
-    f[i] = X_at(0, i, y, x);
-    g[i] = X_at(1, i, y, x);
-    lf[i] = lam_at(0, i, y, x);
-    lg[i] = lam_at(1, i, y, x);
+    f[i] = adj_X<SPLIT, S>(state, kp, 0, i, y, x);
+    g[i] = adj_X<SPLIT, S>(state, kp, 1, i, y, x);
   }
   const NodeMoments m = node_moments<N1>(f, g);
-  double mu_f[5][5], mu_g[3][3];
+  double mu_f[5][5], mu_g[3][3], s = 0.0;
+#pragma unroll
   for (int p = 0; p < 5; ++p)
+#pragma unroll
     for (int q = 0; q < 5; ++q) mu_f[p][q] = 0.0;
+#pragma unroll
   for (int p = 0; p < 3; ++p)
+#pragma unroll
     for (int q = 0; q < 3; ++q) mu_g[p][q] = 0.0;
-  double s = 0.0;
+#pragma unroll
   for (int i = 0; i < Q; ++i) {
+    const double lf = lam1[int64_t(i) * cells + c], lg = lam1[int64_t(Q + i) * cells + c];
     const double xa = L::xi(i / N1), xb = L::xi(i % N1), w = weight<SPLIT>(i);
+#pragma unroll
     for (int p = 0; p <= NF; ++p)
-      for (int q = 0; p + q <= NF; ++q) mu_f[p][q] += lf[i] * w * hn(p, xa) * hn(q, xb);
+#pragma unroll
+      for (int q = 0; p + q <= NF; ++q) mu_f[p][q] += lf * (w * hn(p, xa) * hn(q, xb));
+#pragma unroll
     for (int p = 0; p <= 2; ++p)
-      for (int q = 0; p + q <= 2; ++q) mu_g[p][q] += lg[i] * w * hn(p, xa) * hn(q, xb);
-    s += lf[i] * f[i] + lg[i] * g[i];
-  }
-  double om1;
-  {
-    double bf[5][5], bg[3][3];
-    collision_coeffs<SPLIT, PRM, double>(m, kp, kp.om_scale, kp.Pr, bf, bg, om1);
-  }
-  double mbar[N_MOMENTS];
-  const double mv[N_MOMENTS] = {m.rho, m.jx, m.jy, m.pxx, m.pxy, m.pyy, m.qxxx, m.qxxy, m.qxyy, m.qyyy,
-                                m.g0, m.qgx, m.qgy};
-  for (int r = 0; r < N_MOMENTS + 2; ++r) {
-    D1 md[N_MOMENTS];
-    for (int k = 0; k < N_MOMENTS; ++k) md[k] = D1(mv[k], k == r ? 1.0 : 0.0);
-    const MomentsT<D1> mdual = {md[0], md[1], md[2], md[3], md[4], md[5], md[6],
-                                md[7], md[8], md[9], md[10], md[11], md[12]};
-    // d om_scale / d tau_ref = -om_scale / tau_ref (om_scale = dt / tau_ref [/ p_ref])
-    const D1 oms(kp.om_scale, r == N_MOMENTS ? -kp.om_scale / tau_ref : 0.0);
-    const D1 prd(kp.Pr, r == N_MOMENTS + 1 ? 1.0 : 0.0);
-    D1 bf[5][5], bg[3][3], o1;
-    collision_coeffs<SPLIT, PRM, D1, D1>(mdual, kp, oms, prd, bf, bg, o1);
-    double t = -s * o1.d;
-    for (int p = 0; p <= NF; ++p)
-      for (int q = 0; p + q <= NF; ++q) t += mu_f[p][q] * bf[p][q].d;
-    for (int p = 0; p <= 2; ++p)
-      for (int q = 0; p + q <= 2; ++q) t += mu_g[p][q] * bg[p][q].d;
-    if (r < N_MOMENTS)
-      mbar[r] = t;
-    else if (r == N_MOMENTS)
-      g_tau += t;
-    else
-      g_pr += t;
+#pragma unroll
+      for (int q = 0; p + q <= 2; ++q) mu_g[p][q] += lg * (w * hn(p, xa) * hn(q, xb));
+    s += lf * f[i] + lg * g[i];
   }
 
-  // flux part, then write lam = relaxation + flux cotangents
-  const double keep = 1.0 - om1;
-  const double beta = 0.5 * kp.beta2;
-  for (int d = 0; d < 2; ++d) {
-    for (int i = 0; i < Q; ++i) {
-      const double xa = L::xi(i / N1), xb = L::xi(i % N1);
-      const double xa2 = xa * xa, xb2 = xb * xb;
-      double out;
-      if (d == 0) {
-        out = keep * lf[i] + mbar[0] + mbar[1] * xa + mbar[2] * xb + mbar[3] * xa2 + mbar[4] * xa * xb +
-              mbar[5] * xb2 + mbar[6] * xa2 * xa + mbar[7] * xa2 * xb + mbar[8] * xa * xb2 + mbar[9] * xb2 * xb;
-      } else {
-        out = keep * lg[i] + mbar[10] + mbar[11] * xa + mbar[12] * xb;
-      }
-      if (xa != 0.0) {
-        double Xs[7], lm[5];
-        for (int k = 0; k < 7; ++k) Xs[k] = X_at(d, i, y, wrap_any<BCX>(x - 3 + k, kp.nx));
-        for (int k = 0; k < 5; ++k) lm[k] = lam_at(d, i, y, wrap_any<BCX>(x - 2 + k, kp.nx));
-        out += flux_adjoint<BCX>(Xs, lm, x, kp.nx, kp.kx * xa, beta);
-      }
-      if (xb != 0.0) {
-        double Xs[7], lm[5];
-        for (int k = 0; k < 7; ++k) Xs[k] = X_at(d, i, wrap_any<BCY>(y - 3 + k, kp.ny), x);
-        for (int k = 0; k < 5; ++k) lm[k] = lam_at(d, i, wrap_any<BCY>(y - 2 + k, kp.ny), x);
-        out += flux_adjoint<BCY>(Xs, lm, y, kp.ny, kp.ky * xb, beta);
-      }
-      lam0[int64_t(d * Q + i) * cells + int64_t(y) * kp.nx + x] = out;
-    }
+  // directions r = grp * ADJ_DIRS + k: moments 0..12, 13: tau_ref, 14: Pr
+  using V = DN<ADJ_DIRS>;
+  const double mv[N_MOMENTS] = {m.rho, m.jx, m.jy, m.pxx, m.pxy, m.pyy, m.qxxx, m.qxxy, m.qxyy, m.qyyy,
+                                m.g0, m.qgx, m.qgy};
+  V md[N_MOMENTS];
+  V oms(kp.om_scale), prd(kp.Pr);
+#pragma unroll
+  for (int k = 0; k < N_MOMENTS; ++k) md[k] = V(mv[k]);
+#pragma unroll
+  for (int k = 0; k < ADJ_DIRS; ++k) {
+    const int r = grp * ADJ_DIRS + k;
+#pragma unroll
+    for (int j = 0; j < N_MOMENTS; ++j)
+      if (j == r) md[j].d[k] = 1.0;
+    // om_scale = dt / tau_ref [/ p_ref]:  d om_scale / d tau_ref = -om_scale / tau_ref
+    if (r == N_MOMENTS) oms.d[k] = -kp.om_scale / tau_ref;
+    if (r == N_MOMENTS + 1) prd.d[k] = 1.0;
   }
+  const MomentsT<V> mdual = {md[0], md[1], md[2], md[3], md[4], md[5], md[6],
+                             md[7], md[8], md[9], md[10], md[11], md[12]};
+  V bf[5][5], bg[3][3], o1;
+  collision_coeffs<SPLIT, PRM, V, V>(mdual, kp, oms, prd, bf, bg, o1);
+  if (grp == 0) work[int64_t(N_MOMENTS) * cells + c] = 1.0 - o1.v;
+#pragma unroll
+  for (int k = 0; k < ADJ_DIRS; ++k) {
+    const int r = grp * ADJ_DIRS + k;
+    double t = -s * o1.d[k];
+#pragma unroll
+    for (int p = 0; p <= NF; ++p)
+#pragma unroll
+      for (int q = 0; p + q <= NF; ++q) t += mu_f[p][q] * bf[p][q].d[k];
+#pragma unroll
+    for (int p = 0; p <= 2; ++p)
+#pragma unroll
+      for (int q = 0; p + q <= 2; ++q) t += mu_g[p][q] * bg[p][q].d[k];
+    if (r < N_MOMENTS)
+      work[int64_t(r) * cells + c] = t;
+    else if (r == N_MOMENTS)
+      g_tau += t;
+    else if (r == N_MOMENTS + 1)
+      g_pr += t;
+  }
+}
+
+template <int SPLIT, class S, int BCX, int BCY>
+__device__ inline void plane_adjoint_flux(const typename S::T* __restrict__ state, const double* __restrict__ lam1,
+                                          const double* __restrict__ work, double* __restrict__ lam0,
+                                          const KParams& kp, int pl, int x, int y) {
+  constexpr int N1 = Set<SPLIT>::N1;
+  constexpr int Q = Set<SPLIT>::Q;
+  using L = GH<N1>;
+  const int64_t cells = int64_t(kp.nx) * kp.ny;
+  const int64_t c = int64_t(y) * kp.nx + x;
+  const int d = pl / Q, i = pl % Q;
+  const double xa = L::xi(i / N1), xb = L::xi(i % N1);
+  const double* lp = lam1 + int64_t(pl) * cells;
+  double out = work[int64_t(N_MOMENTS) * cells + c] * lp[c];
+  auto mb = [&](int r) { return work[int64_t(r) * cells + c]; };
+  if (d == 0) {
+    const double xa2 = xa * xa, xb2 = xb * xb;
+    out += mb(0) + mb(1) * xa + mb(2) * xb + mb(3) * xa2 + mb(4) * (xa * xb) + mb(5) * xb2 + mb(6) * (xa2 * xa) +
+           mb(7) * (xa2 * xb) + mb(8) * (xa * xb2) + mb(9) * (xb2 * xb);
+  } else {
+    out += mb(10) + mb(11) * xa + mb(12) * xb;
+  }
+  const double beta = 0.5 * kp.beta2;
+  if (xa != 0.0) {
+    double Xs[7], lm[5];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) Xs[k] = adj_X<SPLIT, S>(state, kp, d, i, y, wrap<BCX>(x - 3 + k, kp.nx));
+#pragma unroll
+    for (int k = 0; k < 5; ++k) lm[k] = lp[int64_t(y) * kp.nx + wrap<BCX>(x - 2 + k, kp.nx)];
+    out += flux_adjoint<BCX>(Xs, lm, x, kp.nx, kp.kx * xa, beta);
+  }
+  if (xb != 0.0) {
+    double Xs[7], lm[5];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) Xs[k] = adj_X<SPLIT, S>(state, kp, d, i, wrap<BCY>(y - 3 + k, kp.ny), x);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) lm[k] = lp[int64_t(wrap<BCY>(y - 2 + k, kp.ny)) * kp.nx + x];
+    out += flux_adjoint<BCY>(Xs, lm, y, kp.ny, kp.ky * xb, beta);
+  }
+  lam0[int64_t(pl) * cells + c] = out;
 }
 
 // ------------------------------------------------------------ readout adjoint

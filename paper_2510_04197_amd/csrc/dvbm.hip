@@ -36,6 +36,10 @@ namespace dvbm {
 //    path the bottleneck).
 constexpr int RED_BLOCKS = 1024;
 constexpr int RED_THREADS = 256;
+// relaxation-part blocks per direction group of the adjoint step (their
+// partials fit the RED_BLOCKS slots of the workspace)
+constexpr int ADJ_RELAX_BLOCKS = 256;
+static_assert(ADJ_RELAX_BLOCKS * ADJ_GROUPS <= RED_BLOCKS, "adjoint partials exceed the workspace");
 #ifndef DVBM_CELL_TX
 #define DVBM_CELL_TX 64
 #endif
@@ -75,14 +79,6 @@ __device__ inline void tile_of_block(int w, int nbx, int nby, int& bx, int& by) 
 #ifndef DVBM_SWEEP
 #define DVBM_SWEEP 1
 #endif
-#ifndef DVBM_LDS_ALL
-#define DVBM_LDS_ALL 0
-#endif
-template <class S>
-struct UseTiles {
-  static constexpr bool value = DVBM_LDS_ALL || sizeof(typename S::T) == 8;
-};
-
 // ------------------------------------------------------------ fused step
 template <int SPLIT, class S, int BCX, int BCY, int PRM>
 __global__ __launch_bounds__(CELL_TX* CELL_TY) void k_collide_advect(const typename S::T* __restrict__ src,
@@ -130,6 +126,10 @@ __device__ inline void sweep_range(int ny, int kseg, int j, int& ya, int& yb) {
 #ifndef DVBM_SWEEP_WPE
 #define DVBM_SWEEP_WPE 2
 #endif
+// Below this many cells a grid has too few strip groups x row ranges to
+// occupy the device, and the per-cell kernel is faster (measured: 256^2 and
+// 512^2 favour it, 1024^2 and larger the sweep).
+constexpr int64_t SWEEP_MIN_CELLS = 3 << 18;
 template <int SPLIT, class S, int BCX, int BCY, int PRM>
 __global__ __launch_bounds__(128 * SWEEP_K) __attribute__((amdgpu_waves_per_eu(DVBM_SWEEP_WPE))) void
 k_collide_advect_sweep(const typename S::T* __restrict__ src, typename S::T* __restrict__ dst, KParams kp,
@@ -329,26 +329,59 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(const double* __restrict
 #endif
 
 // ------------------------------------------------------------ adjoint
-template <int SPLIT, class S, int BCX, int BCY, int PRM>
-__global__ __launch_bounds__(RED_THREADS) void k_adjoint_step(const typename S::T* __restrict__ state,
-                                                              const double* __restrict__ lam1,
-                                                              double* __restrict__ lam0, KParams kp, double tau_ref,
-                                                              double* partials) {
-  const int64_t n = int64_t(kp.nx) * kp.ny;
+// Adjoint step, relaxation part: blockIdx.y is the direction group, the
+// cells are covered grid-stride along x; block partials of (d/dtau_ref,
+// d/dPr) go to partials[4 * (blockIdx.y * gridDim.x + blockIdx.x)].
+template <int SPLIT, class S, int PRM>
+__global__ __launch_bounds__(RED_THREADS) void k_adjoint_relax(const typename S::T* __restrict__ state,
+                                                               const double* __restrict__ lam1,
+                                                               double* __restrict__ work, KParams kp,
+                                                               double tau_ref, double* partials) {
+  const int cells = kp.nx * kp.ny;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < n; c += int64_t(gridDim.x) * blockDim.x) {
-    const int y = int(c / kp.nx), x = int(c % kp.nx);
-    cell_adjoint<SPLIT, S, BCX, BCY, PRM>(state, lam1, lam0, kp, x, y, tau_ref, acc[0], acc[1]);
-  }
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += gridDim.x * blockDim.x)
+    cell_adjoint_relax<SPLIT, S, PRM>(state, lam1, work, kp, c, int(blockIdx.y), tau_ref, acc[0], acc[1]);
   const int mode[4] = {0, 0, 0, 0};
-  block_reduce4(acc, mode, partials + 4 * blockIdx.x);
+  block_reduce4(acc, mode, partials + 4 * (blockIdx.y * gridDim.x + blockIdx.x));
+}
+
+// Adjoint step, flux part and assembly: blockIdx.z is the population plane,
+// rows grid-stride along y, 256 consecutive cells of a row per block.
+template <int SPLIT, class S, int BCX, int BCY>
+__global__ __launch_bounds__(256) void k_adjoint_flux(const typename S::T* __restrict__ state,
+                                                      const double* __restrict__ lam1,
+                                                      const double* __restrict__ work, double* __restrict__ lam0,
+                                                      KParams kp) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= kp.nx) return;
+  for (int y = blockIdx.y; y < kp.ny; y += gridDim.y)
+    plane_adjoint_flux<SPLIT, S, BCX, BCY>(state, lam1, work, lam0, kp, int(blockIdx.z), x, y);
 }
 
 #ifndef DVBM_PART  // non-template kernel: main unit only
-__global__ void k_accumulate2(const double* __restrict__ sums, double* __restrict__ out) {
+// out[0..1] += the sums of the first two entries of nblocks block partials
+// (fixed order, deterministic).
+__global__ __launch_bounds__(RED_THREADS) void k_accumulate2(const double* __restrict__ partials, int nblocks,
+                                                             double* __restrict__ out) {
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+    v[0] += partials[4 * b];
+    v[1] += partials[4 * b + 1];
+  }
+  __shared__ double sh[2][RED_THREADS];
+  sh[0][threadIdx.x] = v[0];
+  sh[1][threadIdx.x] = v[1];
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if (int(threadIdx.x) < s) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
-    out[0] += sums[0];
-    out[1] += sums[1];
+    out[0] += sh[0][0];
+    out[1] += sh[1][0];
   }
 }
 #endif
@@ -436,7 +469,7 @@ std::string check_params(const dvbm_params* p) {
       (p->bc_y != DVBM_PERIODIC && p->bc_y != DVBM_ZERO_GRADIENT))
     return "unknown boundary condition";
   if (p->visc_mode != DVBM_CONST_MU && p->visc_mode != DVBM_CONST_TAU) return "unknown visc_mode";
-  if (p->reserved != 0) return "reserved must be 0";
+  if (p->kernel < DVBM_KERNEL_AUTO || p->kernel > DVBM_KERNEL_TILE) return "unknown kernel";
   if (!(p->dx > 0) || !(p->dy > 0)) return "dx, dy must be > 0";
   if (!(p->R > 0)) return "R must be > 0";
   if (!(p->gamma > 1.0) || !(p->gamma <= 2.0)) return "gamma must lie in (1, 2] (Cv >= D R / 2)";
@@ -448,8 +481,10 @@ std::string check_params(const dvbm_params* p) {
   const double nmax = 2147483647.0;
   if (double(p->nx) * double(p->ny) > nmax) return "nx * ny too large";
   const double pitch = double((int64_t(p->nx) + 63) / 64 * 64);
-  if (pitch * double(p->ny) * storage_bytes(p->storage) * (p->split == 1 ? 16 : 25) > 4294967295.0)
-    return "one distribution (Q * ny * pitch elements) must be smaller than 4 GiB";
+  const double dist = pitch * double(p->ny) * storage_bytes(p->storage) * (p->split == 1 ? 16 : 25);
+  if (dist > 4294967295.0) return "one distribution (Q * ny * pitch elements) must be smaller than 4 GiB";
+  if (p->kernel == DVBM_KERNEL_SWEEP && (p->storage == DVBM_F64 || dist > 2147483648.0))
+    return "the column-sweep kernel needs 32/16-bit storage and a distribution of at most 2 GiB";
   return "";
 }
 
@@ -525,28 +560,43 @@ int sweep_ranges(const void* kern, int ngroups, int ny) {
 // in parallel with the others) and declared extern in the main unit.
 namespace dvbm_launch {
 
+// The kernel a handle's steps use (the AUTO rule of dvbm_kernel).
+inline int step_kernel(const dvbm_handle* h) {
+  if (h->p.kernel != DVBM_KERNEL_AUTO) return h->p.kernel;
+  if (h->p.storage == DVBM_F64) return DVBM_KERNEL_TILE;
+  const uint64_t dist = uint64_t(h->kp.plane) * h->Q * uint64_t(storage_bytes(h->p.storage));
+  if (DVBM_SWEEP && int64_t(h->p.nx) * h->p.ny >= SWEEP_MIN_CELLS && dist <= (uint64_t(1) << 31))
+    return DVBM_KERNEL_SWEEP;
+  return DVBM_KERNEL_CELL;
+}
+
 template <int SPLIT, class S, int BCX, int BCY, int PRM>
 void launch_step_pr(const dvbm_handle* h, const void* src, void* dst) {
   using T = typename S::T;
   const T* s = static_cast<const T*>(src);
   T* d = static_cast<T*>(dst);
-  if constexpr (UseTiles<S>::value) {
+  const int kern_id = step_kernel(h);
+  if (kern_id == DVBM_KERNEL_TILE) {
     const dim3 grid(((h->p.nx + TILE_TX - 1) / TILE_TX) * ((h->p.ny + TILE_TY - 1) / TILE_TY));
     hipLaunchKernelGGL((k_collide_advect_lds<SPLIT, S, BCX, BCY, PRM>), grid, dim3(TILE_TX, TILE_TY), 0, h->stream,
                        s, d, h->kp);
-  } else if (DVBM_SWEEP && uint64_t(h->kp.plane) * h->Q * sizeof(T) <= (uint64_t(1) << 31)) {
-    const auto kern = k_collide_advect_sweep<SPLIT, S, BCX, BCY, PRM>;
-    const int nstrips = (h->p.nx + SWEEP_OWN - 1) / SWEEP_OWN;
-    const int ngroups = (nstrips + SWEEP_K - 1) / SWEEP_K;
-    if (h->sweep_kseg == 0) h->sweep_kseg = sweep_ranges(reinterpret_cast<const void*>(kern), ngroups, h->p.ny);
-    const int total = ngroups * h->sweep_kseg;
-    const dim3 grid(8 * ((total + 7) / 8));
-    hipLaunchKernelGGL(kern, grid, dim3(128 * SWEEP_K), 0, h->stream, s, d, h->kp, ngroups, h->sweep_kseg);
-  } else {
-    const dim3 grid(((h->p.nx + CELL_TX - 1) / CELL_TX) * ((h->p.ny + CELL_TY - 1) / CELL_TY));
-    hipLaunchKernelGGL((k_collide_advect<SPLIT, S, BCX, BCY, PRM>), grid, dim3(CELL_TX, CELL_TY), 0, h->stream, s,
-                       d, h->kp);
+    return;
   }
+  if constexpr (sizeof(T) < 8) {
+    if (kern_id == DVBM_KERNEL_SWEEP) {
+      const auto kern = k_collide_advect_sweep<SPLIT, S, BCX, BCY, PRM>;
+      const int nstrips = (h->p.nx + SWEEP_OWN - 1) / SWEEP_OWN;
+      const int ngroups = (nstrips + SWEEP_K - 1) / SWEEP_K;
+      if (h->sweep_kseg == 0) h->sweep_kseg = sweep_ranges(reinterpret_cast<const void*>(kern), ngroups, h->p.ny);
+      const int total = ngroups * h->sweep_kseg;
+      const dim3 grid(8 * ((total + 7) / 8));
+      hipLaunchKernelGGL(kern, grid, dim3(128 * SWEEP_K), 0, h->stream, s, d, h->kp, ngroups, h->sweep_kseg);
+      return;
+    }
+  }
+  const dim3 grid(((h->p.nx + CELL_TX - 1) / CELL_TX) * ((h->p.ny + CELL_TY - 1) / CELL_TY));
+  hipLaunchKernelGGL((k_collide_advect<SPLIT, S, BCX, BCY, PRM>), grid, dim3(CELL_TX, CELL_TY), 0, h->stream, s, d,
+                     h->kp);
 }
 
 template <int SPLIT, class S, int BCX, int BCY>
@@ -574,41 +624,44 @@ void step(const dvbm_handle* h, const void* src, void* dst) {
 }
 
 template <int SPLIT, class S, int BCX, int BCY>
-void adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, double* lam0);
+void adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, double* lam0, double* work);
 
 template <int SPLIT, class S>
-void adjoint(const dvbm_handle* h, const void* state, const double* lam1, double* lam0) {
+void adjoint(const dvbm_handle* h, const void* state, const double* lam1, double* lam0, double* work) {
   const int bx = h->p.bc_x, by = h->p.bc_y;
   if (bx == DVBM_PERIODIC && by == DVBM_PERIODIC)
-    adjoint_bc<SPLIT, S, BC_PERIODIC, BC_PERIODIC>(h, state, lam1, lam0);
+    adjoint_bc<SPLIT, S, BC_PERIODIC, BC_PERIODIC>(h, state, lam1, lam0, work);
   else if (bx == DVBM_ZERO_GRADIENT && by == DVBM_PERIODIC)
-    adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_PERIODIC>(h, state, lam1, lam0);
+    adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_PERIODIC>(h, state, lam1, lam0, work);
   else if (bx == DVBM_PERIODIC && by == DVBM_ZERO_GRADIENT)
-    adjoint_bc<SPLIT, S, BC_PERIODIC, BC_ZERO_GRADIENT>(h, state, lam1, lam0);
+    adjoint_bc<SPLIT, S, BC_PERIODIC, BC_ZERO_GRADIENT>(h, state, lam1, lam0, work);
   else
-    adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_ZERO_GRADIENT>(h, state, lam1, lam0);
+    adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_ZERO_GRADIENT>(h, state, lam1, lam0, work);
 }
 
 template <int SPLIT, class S, int BCX, int BCY>
-void adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, double* lam0) {
+void adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, double* lam0, double* work) {
   using T = typename S::T;
   const T* s = static_cast<const T*>(state);
   const double tau = h->p.tau_ref;
-  const dim3 grid(RED_BLOCKS), block(RED_THREADS);
+  const dim3 grid(ADJ_RELAX_BLOCKS, ADJ_GROUPS), block(RED_THREADS);
   switch (pr_mode(h->p.Pr)) {
     case PR_UNIT:
-      hipLaunchKernelGGL((k_adjoint_step<SPLIT, S, BCX, BCY, PR_UNIT>), grid, block, 0, h->stream, s, lam1, lam0,
-                         h->kp, tau, h->ws);
+      hipLaunchKernelGGL((k_adjoint_relax<SPLIT, S, PR_UNIT>), grid, block, 0, h->stream, s, lam1, work, h->kp, tau,
+                         h->ws);
       break;
     case PR_LOW:
-      hipLaunchKernelGGL((k_adjoint_step<SPLIT, S, BCX, BCY, PR_LOW>), grid, block, 0, h->stream, s, lam1, lam0,
-                         h->kp, tau, h->ws);
+      hipLaunchKernelGGL((k_adjoint_relax<SPLIT, S, PR_LOW>), grid, block, 0, h->stream, s, lam1, work, h->kp, tau,
+                         h->ws);
       break;
     default:
-      hipLaunchKernelGGL((k_adjoint_step<SPLIT, S, BCX, BCY, PR_HIGH>), grid, block, 0, h->stream, s, lam1, lam0,
-                         h->kp, tau, h->ws);
+      hipLaunchKernelGGL((k_adjoint_relax<SPLIT, S, PR_HIGH>), grid, block, 0, h->stream, s, lam1, work, h->kp, tau,
+                         h->ws);
       break;
   }
+  const dim3 fgrid((h->p.nx + 255) / 256, h->p.ny < 65535 ? h->p.ny : 65535, 2 * Set<SPLIT>::Q);
+  hipLaunchKernelGGL((k_adjoint_flux<SPLIT, S, BCX, BCY>), fgrid, dim3(256), 0, h->stream, s, lam1, work, lam0,
+                     h->kp);
 }
 
 }  // namespace dvbm_launch
@@ -618,14 +671,14 @@ void adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, dou
 template void dvbm_launch::step<(DVBM_PART - 1) / 4 + 1, DVBM_PART_STORE>(const dvbm_handle*, const void*, void*);
 #if (DVBM_PART - 1) % 4 < 2
 template void dvbm_launch::adjoint<(DVBM_PART - 1) / 4 + 1, DVBM_PART_STORE>(const dvbm_handle*, const void*,
-                                                                            const double*, double*);
+                                                                            const double*, double*, double*);
 #endif
 #else
 #define DVBM_EXTERN_STEP(SPLIT, S) \
   extern template void dvbm_launch::step<SPLIT, S>(const dvbm_handle*, const void*, void*);
 #define DVBM_EXTERN_ADJ(SPLIT, S)                                                                          \
   extern template void dvbm_launch::adjoint<SPLIT, S>(const dvbm_handle*, const void*, const double*, \
-                                                      double*);
+                                                      double*, double*);
 DVBM_EXTERN_STEP(1, StoreF64)
 DVBM_EXTERN_STEP(1, StoreF32)
 DVBM_EXTERN_STEP(1, StoreBF16)
@@ -706,8 +759,8 @@ struct EncodeOp {
 
 template <int SPLIT, class S>
 struct AdjointOp {
-  static void run(const dvbm_handle* h, const void* state, const double* lam1, double* lam0) {
-    dvbm_launch::adjoint<SPLIT, S>(h, state, lam1, lam0);
+  static void run(const dvbm_handle* h, const void* state, const double* lam1, double* lam0, double* work) {
+    dvbm_launch::adjoint<SPLIT, S>(h, state, lam1, lam0, work);
   }
 };
 
@@ -925,16 +978,20 @@ static int adjoint_storage_ok(const dvbm_handle* h, const char* who) {
   return DVBM_OK;
 }
 
-int dvbm_adjoint_step(dvbm_handle* h, const void* state_n, const double* lam_np1, double* lam_n, double* dparams) {
-  if (!h || !state_n || !lam_np1 || !lam_n) return fail(DVBM_EINVAL, "dvbm_adjoint_step: NULL argument");
+size_t dvbm_adjoint_work_bytes(const dvbm_params* p) {
+  if (!check_params(p).empty()) return 0;
+  return size_t(ADJ_WORK_ROWS) * size_t(p->nx) * size_t(p->ny) * sizeof(double);
+}
+
+int dvbm_adjoint_step(dvbm_handle* h, const void* state_n, const double* lam_np1, double* lam_n, double* dparams,
+                      void* work) {
+  if (!h || !state_n || !lam_np1 || !lam_n || !work) return fail(DVBM_EINVAL, "dvbm_adjoint_step: NULL argument");
   if (lam_np1 == lam_n) return fail(DVBM_EINVAL, "dvbm_adjoint_step: lam_np1 and lam_n must differ");
   if (int rc = adjoint_storage_ok(h, "dvbm_adjoint_step")) return rc;
-  dispatch_adjoint<AdjointOp>(h->p, h, state_n, lam_np1, lam_n);
-  if (dparams) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, h->stream, h->ws, RED_BLOCKS, 0,
-                       h->ws + 4 * RED_BLOCKS);
-    hipLaunchKernelGGL(k_accumulate2, dim3(1), dim3(64), 0, h->stream, h->ws + 4 * RED_BLOCKS, dparams);
-  }
+  dispatch_adjoint<AdjointOp>(h->p, h, state_n, lam_np1, lam_n, static_cast<double*>(work));
+  if (dparams)
+    hipLaunchKernelGGL(k_accumulate2, dim3(1), dim3(RED_THREADS), 0, h->stream, h->ws, ADJ_RELAX_BLOCKS * ADJ_GROUPS,
+                       dparams);
   HIP_TRY(hipGetLastError());
   return DVBM_OK;
 }

@@ -26,6 +26,7 @@ DVBM_ESTIFF = -4
 STORAGE = {"f64": 0, "f32": 1, "bf16_dev": 2, "fp16_dev": 3}
 BC = {"periodic": 0, "zero_gradient": 1}
 VISC = {"const_mu": 0, "const_tau": 1}
+KERNEL = {"auto": 0, "cell": 1, "sweep": 2, "tile": 3}
 
 # every symbol declared in include/dvbm.h, with (restype, argtypes)
 _P = ctypes.c_void_p
@@ -37,7 +38,7 @@ class Params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("split", ctypes.c_int32),
         ("storage", ctypes.c_int32), ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
-        ("visc_mode", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("visc_mode", ctypes.c_int32), ("kernel", ctypes.c_int32),
         ("dx", _D), ("dy", _D), ("R", _D), ("gamma", _D), ("Pr", _D), ("tau_ref", _D),
         ("p_ref", _D), ("T_ref", _D), ("beta", _D), ("cfl", _D), ("dt", _D),
     ]
@@ -63,7 +64,8 @@ SIGNATURES = {
     "dvbm_set_state_index": (ctypes.c_int, [_P, ctypes.c_int]),
     "dvbm_destroy": (None, [_P]),
     "dvbm_adjoint_bytes": (ctypes.c_size_t, [_PP]),
-    "dvbm_adjoint_step": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "dvbm_adjoint_work_bytes": (ctypes.c_size_t, [_PP]),
+    "dvbm_adjoint_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "dvbm_adjoint_moments": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "dvbm_adjoint_init": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "dvbm_last_error": (ctypes.c_char_p, []),
@@ -106,7 +108,7 @@ def num_populations(split: int) -> int:
 
 def make_params(nx, ny, split=2, storage="f32", bc_x="periodic", bc_y="periodic", visc_mode="const_mu",
                 dx=None, dy=None, R=1.0, gamma=1.4, Pr=0.71, tau_ref=5e-5, p_ref=1.0, T_ref=1.0,
-                beta=1.2, cfl=0.01, dt=0.0) -> Params:
+                beta=1.2, cfl=0.01, dt=0.0, kernel="auto") -> Params:
     lib = load_library()
     p = Params()
     lib.dvbm_params_default(ctypes.byref(p))
@@ -119,6 +121,7 @@ def make_params(nx, ny, split=2, storage="f32", bc_x="periodic", bc_y="periodic"
     p.dy = float(dy if dy is not None else p.dx)
     p.R, p.gamma, p.Pr, p.tau_ref, p.p_ref, p.T_ref = map(float, (R, gamma, Pr, tau_ref, p_ref, T_ref))
     p.beta, p.cfl, p.dt = float(beta), float(cfl), float(dt)
+    p.kernel = KERNEL[kernel] if isinstance(kernel, str) else int(kernel)
     return p
 
 
@@ -222,8 +225,11 @@ class Solver:
     def adjoint_step(self, state: torch.Tensor, lam_next: torch.Tensor, lam: torch.Tensor,
                      dparams: torch.Tensor | None = None):
         """``lam = (dX'/dX)^T lam_next`` at ``state``; ``dparams`` (float64[2]) += (d/dtau_ref, d/dPr)."""
+        if getattr(self, "_adj_work", None) is None:
+            nbytes = self.lib.dvbm_adjoint_work_bytes(ctypes.byref(self.params))
+            self._adj_work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         _check(self.lib.dvbm_adjoint_step(self.handle, _ptr(state), _ptr(lam_next), _ptr(lam),
-                                          _ptr(dparams) if dparams is not None else None))
+                                          _ptr(dparams) if dparams is not None else None, _ptr(self._adj_work)))
 
     def adjoint_moments(self, state: torch.Tensor, d_rho=None, d_ux=None, d_uy=None, d_T=None) -> torch.Tensor:
         """Cotangent of the populations of ``state`` from cotangents of its fields."""

@@ -63,7 +63,7 @@ def test_sizes_and_defaults():
 
 
 @pytest.mark.parametrize("field,value", [("nx", 3), ("split", 3), ("gamma", 2.5), ("beta", 0.9), ("Pr", 0.0),
-                                         ("storage", 7), ("tau_ref", -1.0), ("reserved", 1)])
+                                         ("storage", 7), ("tau_ref", -1.0), ("kernel", 4), ("kernel", -1)])
 def test_invalid_parameters_rejected_before_any_device_work(field, value):
     from paper_2510_04197_amd import dvbm
     lib = dvbm.load_library()
@@ -85,3 +85,16 @@ def test_null_handle_calls_fail_cleanly():
     assert lib.dvbm_moments(None, None, None, None, None, None) == dvbm.DVBM_EINVAL
     assert lib.dvbm_set_state_index(None, 0) == dvbm.DVBM_EINVAL
     lib.dvbm_destroy(None)
+
+
+def test_sweep_kernel_needs_32_or_16_bit_storage():
+    from paper_2510_04197_amd import dvbm
+    lib = dvbm.load_library()
+    for storage, ok in (("f64", False), ("f32", True), ("bf16_dev", True), ("fp16_dev", True)):
+        p = dvbm.make_params(16, 16, storage=storage, kernel="sweep")
+        assert (lib.dvbm_buffer_bytes(ctypes.byref(p)) > 0) == ok, storage
+    # a float32 distribution above 2 GiB: 25 planes x 5120 x 4224 cells x 4 B
+    p = dvbm.make_params(5120, 4224, storage="f32", kernel="sweep")
+    assert lib.dvbm_buffer_bytes(ctypes.byref(p)) == 0
+    p = dvbm.make_params(5120, 4224, storage="f32", kernel="cell")
+    assert lib.dvbm_buffer_bytes(ctypes.byref(p)) > 0

@@ -60,10 +60,11 @@ def test_initial_equilibrium(split, storage, tol):
 CASES = [(split, Pr, bc) for split in (1, 2) for Pr in (0.5, 1.0, 2.0) for bc in ("periodic", "zero_gradient")]
 
 
+@pytest.mark.parametrize("kernel", ("tile", "cell"))
 @pytest.mark.parametrize("split,Pr,bc", CASES)
-def test_steps_fp64(split, Pr, bc):
+def test_steps_fp64(split, Pr, bc, kernel):
     wl = smooth_random(70, 37, seed=2)  # two 64-wide tiles in x with a ragged tail, ragged rows in y
-    s, p = solver(wl, split=split, storage="f64", Pr=Pr, tau_ref=0.02, bc_x=bc, cfl=0.1)
+    s, p = solver(wl, split=split, storage="f64", Pr=Pr, tau_ref=0.02, bc_x=bc, cfl=0.1, kernel=kernel)
     cfg = oracle_cfg(p)
     f0, g0 = O.initial_state(wl.rho, wl.ux, wl.uy, wl.T, cfg)
     s.step(8)
@@ -73,10 +74,11 @@ def test_steps_fp64(split, Pr, bc):
     assert rel(f - f0, fo - f0) < 1e-9 and rel(g - g0, go - g0) < 1e-9
 
 
+@pytest.mark.parametrize("kernel", ("cell", "sweep", "tile"))
 @pytest.mark.parametrize("split,Pr,bc", CASES)
-def test_steps_fp32(split, Pr, bc):
-    wl = smooth_random(70, 37, seed=3)
-    s, p = solver(wl, split=split, storage="f32", Pr=Pr, tau_ref=0.02, bc_x=bc, bc_y=bc, cfl=0.1)
+def test_steps_fp32(split, Pr, bc, kernel):
+    wl = smooth_random(70, 37, seed=3)  # sweep: two 60-column strips, the second ragged; 37 rows in ranges of 3 m
+    s, p = solver(wl, split=split, storage="f32", Pr=Pr, tau_ref=0.02, bc_x=bc, bc_y=bc, cfl=0.1, kernel=kernel)
     cfg = oracle_cfg(p)
     f0, g0 = O.initial_state(wl.rho, wl.ux, wl.uy, wl.T, cfg)
     s.step(8)
@@ -162,10 +164,13 @@ def test_periodic_conservation_fp64(split, Pr):
     assert drift.max() < 1e-16 * 96 * 80 * 200 / 100, drift
 
 
-def test_uniform_state_fixed_point_all_storages():
+@pytest.mark.parametrize("kernel", ("auto", "cell", "sweep", "tile"))
+def test_uniform_state_fixed_point_all_storages(kernel):
     wl = uniform(70, 12, rho=1.1, ux=0.3, uy=-0.1, T=1.05)
     for storage in ("f64", "f32", "bf16_dev", "fp16_dev"):
-        s, _ = solver(wl, split=2, storage=storage, tau_ref=0.02, cfl=0.1)
+        if kernel == "sweep" and storage == "f64":
+            continue
+        s, _ = solver(wl, split=2, storage=storage, tau_ref=0.02, cfl=0.1, kernel=kernel)
         X0 = s.store_populations()
         s.step(10)
         X1 = s.store_populations()
@@ -175,12 +180,30 @@ def test_uniform_state_fixed_point_all_storages():
         assert rel(X1, X0) < tol, storage
 
 
+# ---------------------------------------------------------------- column-sweep geometry
+@pytest.mark.parametrize("nx,ny", ((4, 4), (59, 5), (60, 7), (61, 40), (241, 13), (250, 9), (480, 6)))
+@pytest.mark.parametrize("bc", ("periodic", "zero_gradient"))
+def test_sweep_strips_and_row_ranges_fp32(nx, ny, bc):
+    """Strips of 60 columns in groups of 4 (empty strips at the end of the last group), row ranges of 3 m rows
+    with the last one overlapping its predecessor, grids narrower than a strip."""
+    wl = smooth_random(nx, ny, seed=31, amp_T=0.05)
+    s, p = solver(wl, split=2, storage="f32", Pr=0.6, tau_ref=0.02, bc_x=bc, bc_y=bc, cfl=0.1, kernel="sweep")
+    cfg = oracle_cfg(p)
+    f0, g0 = O.initial_state(wl.rho, wl.ux, wl.uy, wl.T, cfg)
+    s.step(4)
+    f, g = oracle_state(s)
+    fo, go = O.run(f0, g0, cfg, s.dt, 4)
+    assert rel(f, fo) < 1e-5 and rel(g, go) < 1e-5
+    assert rel(f - f0, fo - f0) < 1e-3 and rel(g - g0, go - g0) < 1e-3
+
+
 # ---------------------------------------------------------------- 16-bit deviation storage
+@pytest.mark.parametrize("kernel", ("cell", "sweep", "tile"))
 @pytest.mark.parametrize("split", (1, 2))
 @pytest.mark.parametrize("storage,u", (("bf16_dev", 2.0 ** -8), ("fp16_dev", 2.0 ** -11)))
-def test_deviation_storage_step(split, storage, u):
+def test_deviation_storage_step(split, storage, u, kernel):
     wl = smooth_random(70, 20, seed=8, amp_T=0.05)
-    s, p = solver(wl, split=split, storage=storage, Pr=0.7, tau_ref=0.02, cfl=0.1)
+    s, p = solver(wl, split=split, storage=storage, Pr=0.7, tau_ref=0.02, cfl=0.1, kernel=kernel)
     cfg = oracle_cfg(p)
     f0, g0 = oracle_state(s)  # decoded (already rounded) initial state
     fo_ic, go_ic = O.initial_state(wl.rho, wl.ux, wl.uy, wl.T, cfg)
