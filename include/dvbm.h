@@ -187,9 +187,10 @@ size_t dvbm_adjoint_work_bytes(const dvbm_params* p);
  * buffer in the population layout above, e.g. a checkpoint copy) to
  * X_{n+1}.  When dparams != NULL (device double[2]) it is incremented by
  * (dX_{n+1}/dtau_ref)^T lam_np1 and (dX_{n+1}/dPr)^T lam_np1 (at Pr == 1,
- * where Table I has no quasi-equilibrium, the Pr entry is 0).  work is a
- * caller-owned device array of dvbm_adjoint_work_bytes() bytes (contents
- * overwritten; calls that share it must not overlap).  lam_np1 and lam_n
+ * where Table I has no quasi-equilibrium, the Pr entry is 0), summed in a
+ * fixed order through the handle's workspace.  work is a caller-owned device
+ * array of dvbm_adjoint_work_bytes() bytes (contents overwritten).  Calls on
+ * one handle, or sharing one work array, must not overlap; lam_np1 and lam_n
  * must not overlap.  Asynchronous. */
 int dvbm_adjoint_step(dvbm_handle* h, const void* state_n, const double* lam_np1, double* lam_n,
                       double* dparams, void* work);

@@ -36,10 +36,13 @@ namespace dvbm {
 //    path the bottleneck).
 constexpr int RED_BLOCKS = 1024;
 constexpr int RED_THREADS = 256;
-// relaxation-part blocks per direction group of the adjoint step (their
-// partials fit the RED_BLOCKS slots of the workspace)
-constexpr int ADJ_RELAX_BLOCKS = 256;
-static_assert(ADJ_RELAX_BLOCKS * ADJ_GROUPS <= RED_BLOCKS, "adjoint partials exceed the workspace");
+// blocks of the adjoint relaxation kernel (their partials fit the
+// RED_BLOCKS slots of the workspace)
+constexpr int ADJ_RELAX_BLOCKS = 1024;
+static_assert(ADJ_RELAX_BLOCKS <= RED_BLOCKS, "adjoint partials exceed the workspace");
+// workspace layout (doubles): [0, 4 RED_BLOCKS) block partials, then the
+// final reductions, then (at WS_TICKET) the adjoint's block counter
+constexpr int WS_TICKET = 4 * RED_BLOCKS + 32;
 #ifndef DVBM_CELL_TX
 #define DVBM_CELL_TX 64
 #endif
@@ -329,62 +332,58 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(const double* __restrict
 #endif
 
 // ------------------------------------------------------------ adjoint
-// Adjoint step, relaxation part: blockIdx.y is the direction group, the
-// cells are covered grid-stride along x; block partials of (d/dtau_ref,
-// d/dPr) go to partials[4 * (blockIdx.y * gridDim.x + blockIdx.x)].
+// Adjoint step, relaxation part: one thread per cell (grid-stride).  When
+// dparams != NULL the (d/dtau_ref, d/dPr) block partials go to
+// partials[4 * blockIdx.x], and the last block to finish (counted in
+// *ticket, which it resets) adds their sum, in block order, to dparams.
 template <int SPLIT, class S, int PRM>
 __global__ __launch_bounds__(RED_THREADS) void k_adjoint_relax(const typename S::T* __restrict__ state,
                                                                const double* __restrict__ lam1,
                                                                double* __restrict__ work, KParams kp,
-                                                               double tau_ref, double* partials) {
+                                                               double tau_ref, double* partials,
+                                                               unsigned* ticket, double* dparams) {
   const int cells = kp.nx * kp.ny;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += gridDim.x * blockDim.x)
-    cell_adjoint_relax<SPLIT, S, PRM>(state, lam1, work, kp, c, int(blockIdx.y), tau_ref, acc[0], acc[1]);
+    cell_adjoint_relax<SPLIT, S, PRM>(state, lam1, work, kp, c, tau_ref, acc[0], acc[1]);
+  if (!dparams) return;
   const int mode[4] = {0, 0, 0, 0};
-  block_reduce4(acc, mode, partials + 4 * (blockIdx.y * gridDim.x + blockIdx.x));
+  block_reduce4(acc, mode, partials + 4 * blockIdx.x);
+  __shared__ bool last;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < int(gridDim.x); b += blockDim.x) {
+    v[0] += __hip_atomic_load(partials + 4 * b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    v[1] += __hip_atomic_load(partials + 4 * b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  double tot[4];
+  block_reduce4(v, mode, tot);
+  if (threadIdx.x == 0) {
+    dparams[0] += tot[0];
+    dparams[1] += tot[1];
+    *ticket = 0u;
+  }
 }
 
-// Adjoint step, flux part and assembly: blockIdx.z is the population plane,
-// rows grid-stride along y, 256 consecutive cells of a row per block.
+// Adjoint step, flux part: blockIdx.x is the strip of ADJ_STRIP cells,
+// blockIdx.z the population plane; the 4 waves of a block take rows
+// 4 blockIdx.y + w, grid-stride along y.
 template <int SPLIT, class S, int BCX, int BCY>
 __global__ __launch_bounds__(256) void k_adjoint_flux(const typename S::T* __restrict__ state,
                                                       const double* __restrict__ lam1,
                                                       const double* __restrict__ work, double* __restrict__ lam0,
                                                       KParams kp) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= kp.nx) return;
-  for (int y = blockIdx.y; y < kp.ny; y += gridDim.y)
-    plane_adjoint_flux<SPLIT, S, BCX, BCY>(state, lam1, work, lam0, kp, int(blockIdx.z), x, y);
+  const int w = threadIdx.x / 64;
+  for (int y = 4 * blockIdx.y + w; y < kp.ny; y += 4 * gridDim.y)
+    strip_adjoint_flux<SPLIT, S, BCX, BCY>(state, lam1, work, lam0, kp, int(blockIdx.z), blockIdx.x * ADJ_STRIP, y);
 }
 
-#ifndef DVBM_PART  // non-template kernel: main unit only
-// out[0..1] += the sums of the first two entries of nblocks block partials
-// (fixed order, deterministic).
-__global__ __launch_bounds__(RED_THREADS) void k_accumulate2(const double* __restrict__ partials, int nblocks,
-                                                             double* __restrict__ out) {
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
-    v[0] += partials[4 * b];
-    v[1] += partials[4 * b + 1];
-  }
-  __shared__ double sh[2][RED_THREADS];
-  sh[0][threadIdx.x] = v[0];
-  sh[1][threadIdx.x] = v[1];
-  __syncthreads();
-  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
-    if (int(threadIdx.x) < s) {
-      sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
-      sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    out[0] += sh[0][0];
-    out[1] += sh[1][0];
-  }
-}
-#endif
 
 template <int SPLIT, class S>
 __global__ __launch_bounds__(256) void k_adjoint_readout(const typename S::T* __restrict__ state,
@@ -624,42 +623,49 @@ void step(const dvbm_handle* h, const void* src, void* dst) {
 }
 
 template <int SPLIT, class S, int BCX, int BCY>
-void adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, double* lam0, double* work);
+void adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, double* lam0, double* dparams,
+                double* work);
 
 template <int SPLIT, class S>
-void adjoint(const dvbm_handle* h, const void* state, const double* lam1, double* lam0, double* work) {
+void adjoint(const dvbm_handle* h, const void* state, const double* lam1, double* lam0, double* dparams,
+             double* work) {
   const int bx = h->p.bc_x, by = h->p.bc_y;
   if (bx == DVBM_PERIODIC && by == DVBM_PERIODIC)
-    adjoint_bc<SPLIT, S, BC_PERIODIC, BC_PERIODIC>(h, state, lam1, lam0, work);
+    adjoint_bc<SPLIT, S, BC_PERIODIC, BC_PERIODIC>(h, state, lam1, lam0, dparams, work);
   else if (bx == DVBM_ZERO_GRADIENT && by == DVBM_PERIODIC)
-    adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_PERIODIC>(h, state, lam1, lam0, work);
+    adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_PERIODIC>(h, state, lam1, lam0, dparams, work);
   else if (bx == DVBM_PERIODIC && by == DVBM_ZERO_GRADIENT)
-    adjoint_bc<SPLIT, S, BC_PERIODIC, BC_ZERO_GRADIENT>(h, state, lam1, lam0, work);
+    adjoint_bc<SPLIT, S, BC_PERIODIC, BC_ZERO_GRADIENT>(h, state, lam1, lam0, dparams, work);
   else
-    adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_ZERO_GRADIENT>(h, state, lam1, lam0, work);
+    adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_ZERO_GRADIENT>(h, state, lam1, lam0, dparams, work);
 }
 
 template <int SPLIT, class S, int BCX, int BCY>
-void adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, double* lam0, double* work) {
+void adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, double* lam0, double* dparams,
+                double* work) {
   using T = typename S::T;
   const T* s = static_cast<const T*>(state);
   const double tau = h->p.tau_ref;
-  const dim3 grid(ADJ_RELAX_BLOCKS, ADJ_GROUPS), block(RED_THREADS);
+  unsigned* ticket = reinterpret_cast<unsigned*>(h->ws + WS_TICKET);
+  const int64_t cells = int64_t(h->p.nx) * h->p.ny;
+  const int64_t nb = (cells + RED_THREADS - 1) / RED_THREADS;
+  const dim3 grid(unsigned(nb < ADJ_RELAX_BLOCKS ? nb : ADJ_RELAX_BLOCKS)), block(RED_THREADS);
   switch (pr_mode(h->p.Pr)) {
     case PR_UNIT:
       hipLaunchKernelGGL((k_adjoint_relax<SPLIT, S, PR_UNIT>), grid, block, 0, h->stream, s, lam1, work, h->kp, tau,
-                         h->ws);
+                         h->ws, ticket, dparams);
       break;
     case PR_LOW:
       hipLaunchKernelGGL((k_adjoint_relax<SPLIT, S, PR_LOW>), grid, block, 0, h->stream, s, lam1, work, h->kp, tau,
-                         h->ws);
+                         h->ws, ticket, dparams);
       break;
     default:
       hipLaunchKernelGGL((k_adjoint_relax<SPLIT, S, PR_HIGH>), grid, block, 0, h->stream, s, lam1, work, h->kp, tau,
-                         h->ws);
+                         h->ws, ticket, dparams);
       break;
   }
-  const dim3 fgrid((h->p.nx + 255) / 256, h->p.ny < 65535 ? h->p.ny : 65535, 2 * Set<SPLIT>::Q);
+  const int ry = (h->p.ny + 3) / 4;
+  const dim3 fgrid((h->p.nx + ADJ_STRIP - 1) / ADJ_STRIP, ry < 65535 ? ry : 65535, 2 * Set<SPLIT>::Q);
   hipLaunchKernelGGL((k_adjoint_flux<SPLIT, S, BCX, BCY>), fgrid, dim3(256), 0, h->stream, s, lam1, work, lam0,
                      h->kp);
 }
@@ -671,14 +677,15 @@ void adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, dou
 template void dvbm_launch::step<(DVBM_PART - 1) / 4 + 1, DVBM_PART_STORE>(const dvbm_handle*, const void*, void*);
 #if (DVBM_PART - 1) % 4 < 2
 template void dvbm_launch::adjoint<(DVBM_PART - 1) / 4 + 1, DVBM_PART_STORE>(const dvbm_handle*, const void*,
-                                                                            const double*, double*, double*);
+                                                                            const double*, double*, double*,
+                                                                            double*);
 #endif
 #else
 #define DVBM_EXTERN_STEP(SPLIT, S) \
   extern template void dvbm_launch::step<SPLIT, S>(const dvbm_handle*, const void*, void*);
 #define DVBM_EXTERN_ADJ(SPLIT, S)                                                                          \
   extern template void dvbm_launch::adjoint<SPLIT, S>(const dvbm_handle*, const void*, const double*, \
-                                                      double*, double*);
+                                                      double*, double*, double*);
 DVBM_EXTERN_STEP(1, StoreF64)
 DVBM_EXTERN_STEP(1, StoreF32)
 DVBM_EXTERN_STEP(1, StoreBF16)
@@ -759,8 +766,9 @@ struct EncodeOp {
 
 template <int SPLIT, class S>
 struct AdjointOp {
-  static void run(const dvbm_handle* h, const void* state, const double* lam1, double* lam0, double* work) {
-    dvbm_launch::adjoint<SPLIT, S>(h, state, lam1, lam0, work);
+  static void run(const dvbm_handle* h, const void* state, const double* lam1, double* lam0, double* dparams,
+                  double* work) {
+    dvbm_launch::adjoint<SPLIT, S>(h, state, lam1, lam0, dparams, work);
   }
 };
 
@@ -899,8 +907,13 @@ int dvbm_init(const dvbm_params* p, const double* rho, const double* ux, const d
   h->ws = ws;
   h->stream = s;
   h->sweep_kseg = 0;
+  hipError_t e = hipMemsetAsync(ws + WS_TICKET, 0, sizeof(double), s);  // the adjoint's block counter
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "dvbm_init: workspace");
+  }
   dispatch<InitOp>(h->p, h, rho, ux, uy, T, buf0);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     delete h;
@@ -988,10 +1001,7 @@ int dvbm_adjoint_step(dvbm_handle* h, const void* state_n, const double* lam_np1
   if (!h || !state_n || !lam_np1 || !lam_n || !work) return fail(DVBM_EINVAL, "dvbm_adjoint_step: NULL argument");
   if (lam_np1 == lam_n) return fail(DVBM_EINVAL, "dvbm_adjoint_step: lam_np1 and lam_n must differ");
   if (int rc = adjoint_storage_ok(h, "dvbm_adjoint_step")) return rc;
-  dispatch_adjoint<AdjointOp>(h->p, h, state_n, lam_np1, lam_n, static_cast<double*>(work));
-  if (dparams)
-    hipLaunchKernelGGL(k_accumulate2, dim3(1), dim3(RED_THREADS), 0, h->stream, h->ws, ADJ_RELAX_BLOCKS * ADJ_GROUPS,
-                       dparams);
+  dispatch_adjoint<AdjointOp>(h->p, h, state_n, lam_np1, lam_n, dparams, static_cast<double*>(work));
   HIP_TRY(hipGetLastError());
   return DVBM_OK;
 }
