@@ -168,8 +168,11 @@ def write_profiles(trace_dir: str, fetch_csv: str, write_csv: str, bench_json: s
         for r in rows:
             fh.write(f"| `{r['Name'][:110]}` | {r['Calls']} | {float(r['AverageNs']):.0f} | {r['TotalDurationNs']} |\n")
         ms_ev = line["ms_per_step"]
-        fh.write(f"\nThe table averages every launch of a kernel instance (the adjoint measurement also launches "
-                 f"the step kernel on its 256 x 256 grid). The {len(durs[gmax])} launches of {kname} on the "
+        other = sorted(g for g in durs if g != gmax)
+        note = (f" (the same instance was also launched with grids of {', '.join(map(str, other))} threads)"
+                if other else "")
+        fh.write(f"\nThe table averages every launch of a kernel instance{note}. The {len(durs[gmax])} launches "
+                 f"of {kname} on the "
                  f"{line['config']['nx']} x {line['config']['ny']} grid ({gmax} threads) average {avg_ns:.0f} ns; "
                  f"the bench line of the same run times it at {ms_ev * 1e6:.0f} ns per launch with HIP events "
                  f"on the solver stream ("
