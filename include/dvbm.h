@@ -139,6 +139,12 @@ int dvbm_init(const dvbm_params* p, const double* rho, const double* ux, const d
  * launch per step, ping-ponging between the two buffers).  Asynchronous. */
 int dvbm_step(dvbm_handle* h, int64_t nsteps);
 
+/* One time step from the population buffer src into dst (device buffers of
+ * dvbm_buffer_bytes() in the layout above, e.g. checkpoint copies; they must
+ * not overlap).  The handle's own state and buffers are not touched.
+ * Asynchronous. */
+int dvbm_step_from(dvbm_handle* h, const void* src, void* dst);
+
 /*
  * Macroscopic fields and global sums of the current state (Eqs.
  * eq_quadratur1-3).  rho, ux, uy, T: device float64 arrays of ny*nx or NULL.

@@ -49,16 +49,16 @@ class _Rollout(torch.autograd.Function):
         lam_tmp = torch.empty_like(lam)
         dparams = torch.zeros(2, dtype=torch.float64, device=lam.device)
         nsteps, K = ctx.nsteps, ctx.K
+        # room for the recomputed states of one segment (the checkpoint is the first)
+        seg_states = torch.empty((max(K - 1, 1), s.buffers[0].numel()), dtype=torch.uint8, device=lam.device)
         for seg in reversed(range(len(ctx.ckpts))):
             n0 = seg * K
             n1 = min(n0 + K, nsteps)
             # recompute the states n0 .. n1-1 of this segment from its checkpoint
-            idx = s.state_index
-            s.buffers[idx].copy_(ctx.ckpts[seg])
             states = [ctx.ckpts[seg]]
-            for _ in range(n1 - n0 - 1):
-                s.step(1)
-                states.append(s.state_buffer.clone())
+            for j in range(n1 - n0 - 1):
+                s.step_from(states[-1], seg_states[j])
+                states.append(seg_states[j])
             for st in reversed(states):
                 s.adjoint_step(st, lam, lam_tmp, dparams)
                 lam, lam_tmp = lam_tmp, lam

@@ -429,29 +429,59 @@ __device__ inline void cell_adjoint_relax(const typename S::T* __restrict__ stat
     g[i] = adj_X<SPLIT, S>(state, kp, 1, i, y, x);
   }
   const NodeMoments m = node_moments<N1>(f, g);
+  // mu[p][q] = sum_i lam'_i w_i He_p(xi_a)/p! He_q(xi_b)/q!, factorised over the
+  // tensor-product set: t[a][q] = sum_b lam'_(a,b) w_b He_q(xi_b)/q!, then
+  // mu[p][q] = sum_a w_a He_p(xi_a)/p! t[a][q]
   double mu_f[5][5], mu_g[3][3], s = 0.0;
+  double tf[N1][NF + 1], tg[N1][3];
+#pragma unroll
+  for (int a = 0; a < N1; ++a) {
+#pragma unroll
+    for (int q = 0; q <= NF; ++q) tf[a][q] = 0.0;
+#pragma unroll
+    for (int q = 0; q <= 2; ++q) tg[a][q] = 0.0;
+#pragma unroll
+    for (int b = 0; b < N1; ++b) {
+      const int i = a * N1 + b;
+      const double lf = lam1[int64_t(i) * cells + c], lg = lam1[int64_t(Q + i) * cells + c];
+      const double xb = L::xi(b), wb = L::w(b);
+#pragma unroll
+      for (int q = 0; q <= NF; ++q) {
+        const double h = wb * hn(q, xb);
+        if (h != 0.0) tf[a][q] += lf * h;
+      }
+#pragma unroll
+      for (int q = 0; q <= 2; ++q) {
+        const double h = wb * hn(q, xb);
+        if (h != 0.0) tg[a][q] += lg * h;
+      }
+      s += lf * f[i] + lg * g[i];
+    }
+  }
 #pragma unroll
   for (int p = 0; p < 5; ++p)
 #pragma unroll
-    for (int q = 0; q < 5; ++q) mu_f[p][q] = 0.0;
+    for (int q = 0; q < 5; ++q) {
+      mu_f[p][q] = 0.0;
+      if (p + q > NF) continue;
+#pragma unroll
+      for (int a = 0; a < N1; ++a) {
+        const double h = L::w(a) * hn(p, L::xi(a));
+        if (h != 0.0) mu_f[p][q] += h * tf[a][q];
+      }
+    }
 #pragma unroll
   for (int p = 0; p < 3; ++p)
 #pragma unroll
-    for (int q = 0; q < 3; ++q) mu_g[p][q] = 0.0;
+    for (int q = 0; q < 3; ++q) {
+      mu_g[p][q] = 0.0;
+      if (p + q > 2) continue;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const double lf = lam1[int64_t(i) * cells + c], lg = lam1[int64_t(Q + i) * cells + c];
-    const double xa = L::xi(i / N1), xb = L::xi(i % N1), w = weight<SPLIT>(i);
-#pragma unroll
-    for (int p = 0; p <= NF; ++p)
-#pragma unroll
-      for (int q = 0; p + q <= NF; ++q) mu_f[p][q] += lf * (w * hn(p, xa) * hn(q, xb));
-#pragma unroll
-    for (int p = 0; p <= 2; ++p)
-#pragma unroll
-      for (int q = 0; p + q <= 2; ++q) mu_g[p][q] += lg * (w * hn(p, xa) * hn(q, xb));
-    s += lf * f[i] + lg * g[i];
-  }
+      for (int a = 0; a < N1; ++a) {
+        const double h = L::w(a) * hn(p, L::xi(a));
+        if (h != 0.0) mu_g[p][q] += h * tg[a][q];
+      }
+    }
   double mbar[N_MOMENTS], d_oms, d_pr, om1;
   coeffs_vjp<SPLIT, PRM>(m, kp, kp.om_scale, kp.Pr, mu_f, mu_g, s, mbar, d_oms, d_pr, om1);
 #pragma unroll

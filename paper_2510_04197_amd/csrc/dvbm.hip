@@ -934,6 +934,14 @@ int dvbm_step(dvbm_handle* h, int64_t nsteps) {
   return DVBM_OK;
 }
 
+int dvbm_step_from(dvbm_handle* h, const void* src, void* dst) {
+  if (!h || !src || !dst) return fail(DVBM_EINVAL, "dvbm_step_from: NULL argument");
+  if (src == dst) return fail(DVBM_EINVAL, "dvbm_step_from: src and dst must differ");
+  dispatch<StepOp>(h->p, h, src, dst);
+  HIP_TRY(hipGetLastError());
+  return DVBM_OK;
+}
+
 int dvbm_moments(dvbm_handle* h, double* rho, double* ux, double* uy, double* T, double* sums_host) {
   if (!h) return fail(DVBM_EINVAL, "dvbm_moments: NULL handle");
   dispatch<MomentsOp>(h->p, h, h->buf[h->cur], rho, ux, uy, T, h->ws);

@@ -55,6 +55,7 @@ SIGNATURES = {
     "dvbm_workspace_bytes": (ctypes.c_size_t, [_PP]),
     "dvbm_init": (ctypes.c_int, [_PP, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
     "dvbm_step": (ctypes.c_int, [_P, ctypes.c_int64]),
+    "dvbm_step_from": (ctypes.c_int, [_P, _P, _P]),
     "dvbm_moments": (ctypes.c_int, [_P, _P, _P, _P, _P, _DP]),
     "dvbm_load_populations": (ctypes.c_int, [_P, _P]),
     "dvbm_store_populations": (ctypes.c_int, [_P, _P]),
@@ -173,6 +174,10 @@ class Solver:
     # ------------------------------------------------------------------ stepping
     def step(self, nsteps: int = 1):
         _check(self.lib.dvbm_step(self.handle, int(nsteps)))
+
+    def step_from(self, src: torch.Tensor, dst: torch.Tensor):
+        """One step from the population buffer ``src`` into ``dst``; the solver's own state is unchanged."""
+        _check(self.lib.dvbm_step_from(self.handle, _ptr(src), _ptr(dst)))
 
     @property
     def dt(self) -> float:

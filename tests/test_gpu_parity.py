@@ -9,6 +9,7 @@ Tolerances (relative L2 over all populations of both distributions):
   times the norm of the deviation, plus float32 arithmetic.
 """
 
+import ctypes
 import math
 
 import numpy as np
@@ -295,3 +296,25 @@ def test_stiff_relaxation_rejected():
     with pytest.raises(DVBMError) as e:
         solver(wl, tau_ref=1e-6, cfl=0.5)
     assert e.value.code == dvbm.DVBM_ESTIFF
+
+
+@pytest.mark.parametrize("storage", ("f64", "f32", "bf16_dev"))
+def test_step_from_matches_step(storage):
+    """dvbm_step_from(src, dst) computes the same step as dvbm_step and leaves the handle's state alone."""
+    wl = smooth_random(70, 37, seed=12)
+    s, p = solver(wl, split=2, storage=storage, Pr=0.7, tau_ref=0.02, cfl=0.1)
+    s.step(2)
+    idx = s.state_index
+    src = s.state_buffer.clone()
+    dst = torch.empty_like(src)
+    s.step_from(src, dst)
+    assert s.state_index == idx and torch.equal(s.state_buffer, src)
+    s.step(1)
+    # compare the cells only (the pitch padding of the two buffers holds unrelated bytes)
+    dt = {"f64": torch.float64, "f32": torch.float32, "bf16_dev": torch.int16}[storage]
+    pitch = dvbm.load_library().dvbm_pitch(ctypes.byref(p))
+
+    def cells(buf):
+        return buf.view(dt).reshape(2 * s.Q, p.ny, pitch)[:, :, : p.nx]
+
+    assert torch.equal(cells(s.state_buffer), cells(dst))
