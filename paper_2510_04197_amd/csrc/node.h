@@ -64,8 +64,8 @@ struct StoreBF16 {
   using C = float;
   static constexpr bool dev = true;
   __device__ static C raw(T v) { return __uint_as_float(uint32_t(v) << 16); }
-  __device__ static T enc(C x, C winv, C r) {
-    const float d = x * winv - r;
+  __device__ static T enc(C x, C winv, C r) { return enc_dev(x * winv - r); }
+  __device__ static T enc_dev(C d) {  // a deviation already in units of w
     uint32_t u = __float_as_uint(d);
     u += 0x7FFFu + ((u >> 16) & 1u);
     return T(u >> 16);
@@ -79,6 +79,7 @@ struct StoreF16 {
   static constexpr bool dev = true;
   __device__ static C raw(T v) { return float(v); }
   __device__ static T enc(C x, C winv, C r) { return T(x * winv - r); }
+  __device__ static T enc_dev(C d) { return T(d); }  // a deviation already in units of w
 };
 
 // ------------------------------------------------------------ small helpers

@@ -274,15 +274,25 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
         constexpr double w = GH<N1>::w(xa) * GH<N1>::w(ybn);
         R* wn = win[i];
         const R c0 = cen[i];
-        const R rr = S::dev ? rest(i) : R(0);
-        const R X = S::dev ? R(w) * (rr + c0) : c0;
-        // collision: (1 - om1) X + w_i sum_p He_p(xi_a)/p! c_p
-        R xn = keep * X;
+        // collision: (1 - om1) X + w_i sum_p He_p(xi_a)/p! c_p; the 16-bit formats work in
+        // deviation units d = X/w - r:  d' = (1 - om1) d - om1 r + sum_p He_p(xi_a)/p! c_p
+        R xn;
+        if (S::dev) {
+          xn = keep * c0 - om1 * rest(i);
 #pragma unroll
-        for (int p = 0; p <= 4; ++p) {
-          if (p > N) continue;
-          const double h = hn(p, xv);
-          if (h != 0.0) xn += R(w * h) * c[p];
+          for (int p = 0; p <= 4; ++p) {
+            if (p > N) continue;
+            const double h = hn(p, xv);
+            if (h != 0.0) xn += R(h) * c[p];
+          }
+        } else {
+          xn = keep * c0;
+#pragma unroll
+          for (int p = 0; p <= 4; ++p) {
+            if (p > N) continue;
+            const double h = hn(p, xv);
+            if (h != 0.0) xn += R(w * h) * c[p];
+          }
         }
         // advection: -(dt/dx) v_x (X_{x+1/2} - X_{x-1/2}) - (dt/dy) v_y (X_{y+1/2} - X_{y-1/2})
         R div = R(0);
@@ -300,8 +310,11 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
           div += ky * R(xb) * (fa - fbelow[i]);
           fbelow[i] = fa;
         }
-        xn -= S::dev ? R(w) * div : div;
-        Buf<T>::st(rsrc_dst, uint32_t(i) * plane_bytes + r_st, vo_st, S::enc(xn, R(1.0 / w), rr));
+        xn -= div;  // stored values and deviations share the flux form (L is homogeneous)
+        if constexpr (S::dev)
+          Buf<T>::st(rsrc_dst, uint32_t(i) * plane_bytes + r_st, vo_st, S::enc_dev(xn));
+        else
+          Buf<T>::st(rsrc_dst, uint32_t(i) * plane_bytes + r_st, vo_st, S::enc(xn, R(1), R(0)));
         // the window drops its first row; that register receives the row it now needs
         wn[P] = load(i, xb > 0.0 ? r_p2 : r_p3);
       });
