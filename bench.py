@@ -255,7 +255,7 @@ def precision_errors(fields, ref):
 def adjoint_cost(device, n=256, nsteps=200, storage="f32", Ks=(10, 50)):
     """Gradient of L = sum (T(200 steps) - T_target)^2 w.r.t. T0, tau_ref, Pr on the 256^2 periodic
     Gaussian-bump workload: time of forward + checkpointed recomputation + reverse sweep, divided by
-    the time of the plain forward run."""
+    the time of the plain forward run (and with the recomputation on a second stream)."""
     import numpy as np
     import torch
 
@@ -279,11 +279,11 @@ def adjoint_cost(device, n=256, nsteps=200, storage="f32", Ks=(10, 50)):
         s.close()
         return T
 
-    def with_gradient(K):
+    def with_gradient(K, overlap=False):
         T0t = torch.tensor(T0, device=device, requires_grad=True)
         tau = torch.tensor(tau0, dtype=torch.float64, requires_grad=True)
         prt = torch.tensor(Pr, dtype=torch.float64, requires_grad=True)
-        out = rollout_temperature(T0t, tau, prt, ones, zeros, zeros, nsteps, K=K, **kw)
+        out = rollout_temperature(T0t, tau, prt, ones, zeros, zeros, nsteps, K=K, overlap=overlap, **kw)
         ((out - tgt) ** 2).sum().backward()
         return T0t.grad
 
@@ -303,6 +303,9 @@ def adjoint_cost(device, n=256, nsteps=200, storage="f32", Ks=(10, 50)):
         t = timed(lambda: with_gradient(K))
         res[f"K{K}_s"] = t
         res[f"K{K}_ratio"] = t / t_fwd
+    # the same with the recomputation on a second stream
+    t = timed(lambda: with_gradient(Ks[0], overlap=True))
+    res[f"K{Ks[0]}_overlap_ratio"] = t / t_fwd
     return res
 
 

@@ -4,7 +4,8 @@
 DDF-QE DVBM from the equilibrium of ``(rho0, u0, T0)`` and returns the final
 temperature field; its backward pass is the discrete adjoint of the library
 (``dvbm_adjoint_*``), with checkpoints every ``K`` steps and recomputation of
-each segment's states during the reverse sweep. The time step is held fixed
+each segment's states during the reverse sweep (optionally on a second stream,
+one segment ahead of the sweep). The time step is held fixed
 (it must be given explicitly), so the gradient is that of the fixed-dt map.
 
 Argument marshalling only: forward and reverse sweeps run in the HIP kernels.
@@ -19,7 +20,7 @@ from .dvbm import Solver, make_params
 
 class _Rollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, T0, tau_ref, Pr, rho0, ux0, uy0, nsteps, K, params_kw):
+    def forward(ctx, T0, tau_ref, Pr, rho0, ux0, uy0, nsteps, K, overlap, params_kw):
         if not params_kw.get("dt", 0.0) > 0.0:
             raise ValueError("rollout_temperature needs an explicit dt > 0")
         ny, nx = T0.shape
@@ -36,7 +37,7 @@ class _Rollout(torch.autograd.Function):
         ctx.solver = s
         ctx.ckpts = ckpts
         ctx.final = s.state_buffer.clone()
-        ctx.nsteps, ctx.K = nsteps, K
+        ctx.nsteps, ctx.K, ctx.overlap = nsteps, K, overlap
         ctx.fields0 = (rho0, ux0, uy0, T0.detach())
         ctx.pdev = (tau_ref.device if torch.is_tensor(tau_ref) else None,
                     Pr.device if torch.is_tensor(Pr) else None)
@@ -45,37 +46,80 @@ class _Rollout(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gT):
         s: Solver = ctx.solver
+        dev = gT.device
         lam = s.adjoint_moments(ctx.final, d_T=gT.contiguous())
         lam_tmp = torch.empty_like(lam)
-        dparams = torch.zeros(2, dtype=torch.float64, device=lam.device)
+        dparams = torch.zeros(2, dtype=torch.float64, device=dev)
         nsteps, K = ctx.nsteps, ctx.K
-        # room for the recomputed states of one segment (the checkpoint is the first)
-        seg_states = torch.empty((max(K - 1, 1), s.buffers[0].numel()), dtype=torch.uint8, device=lam.device)
-        for seg in reversed(range(len(ctx.ckpts))):
+        nseg = len(ctx.ckpts)
+        # With overlap, the states of segment j-1 are recomputed from its
+        # checkpoint on a side stream, by a second handle, while the main stream
+        # runs the reverse sweep over segment j: two buffers of K-1 states take
+        # turns.  Without, one buffer and one stream, recomputing after each sweep.
+        main = s.stream
+        nb = s.buffers[0].numel()
+        if ctx.overlap:
+            side = torch.cuda.Stream(device=dev)
+            side.wait_stream(main)  # the checkpoints and the forward state are ready
+            r = Solver(s.params, *ctx.fields0, device=dev, stream=side)
+            bufs = [torch.empty((max(K - 1, 1), nb), dtype=torch.uint8, device=dev) for _ in range(2)]
+        else:
+            side, r = main, s
+            bufs = [torch.empty((max(K - 1, 1), nb), dtype=torch.uint8, device=dev)] * 2
+        ready = [torch.cuda.Event() for _ in range(nseg)]
+        free = [None, None]  # event on main after the last reverse sweep that read bufs[k]
+
+        def seg_range(seg):
             n0 = seg * K
-            n1 = min(n0 + K, nsteps)
-            # recompute the states n0 .. n1-1 of this segment from its checkpoint
+            return n0, min(n0 + K, nsteps)
+
+        def recompute(seg):
+            n0, n1 = seg_range(seg)
+            buf = bufs[seg % 2]
+            if free[seg % 2] is not None:
+                side.wait_event(free[seg % 2])
             states = [ctx.ckpts[seg]]
             for j in range(n1 - n0 - 1):
-                s.step_from(states[-1], seg_states[j])
-                states.append(seg_states[j])
+                r.step_from(states[-1], buf[j])
+                states.append(buf[j])
+            ready[seg].record(side)
+            return states
+
+        pending = {nseg - 1: recompute(nseg - 1)}
+        for seg in reversed(range(nseg)):
+            states = pending.pop(seg)
+            if ctx.overlap and seg > 0:
+                pending[seg - 1] = recompute(seg - 1)
+            main.wait_event(ready[seg])
             for st in reversed(states):
                 s.adjoint_step(st, lam, lam_tmp, dparams)
                 lam, lam_tmp = lam_tmp, lam
+            ev = torch.cuda.Event()
+            ev.record(main)
+            free[seg % 2] = ev
+            if not ctx.overlap and seg > 0:
+                pending[seg - 1] = recompute(seg - 1)
+        if ctx.overlap:
+            main.wait_stream(side)
+            r.close()
         g = s.adjoint_init(lam, *ctx.fields0, which=("T",))["T"]
         s.close()
         dtau = dparams[0].to(ctx.pdev[0]) if ctx.pdev[0] is not None else None
         dpr = dparams[1].to(ctx.pdev[1]) if ctx.pdev[1] is not None else None
-        return g, dtau, dpr, None, None, None, None, None, None
+        return g, dtau, dpr, None, None, None, None, None, None, None
 
 
 def rollout_temperature(T0: torch.Tensor, tau_ref: torch.Tensor, Pr: torch.Tensor, rho0, ux0, uy0,
-                        nsteps: int, K: int = 10, **params_kw) -> torch.Tensor:
+                        nsteps: int, K: int = 10, overlap: bool = False, **params_kw) -> torch.Tensor:
     """Final temperature after ``nsteps`` steps; differentiable in ``T0``, ``tau_ref`` and ``Pr``.
 
     ``T0`` is a float64 CUDA tensor of shape ``(ny, nx)``; ``tau_ref`` and
     ``Pr`` are 0-dim tensors; ``params_kw`` are the remaining solver
     parameters of :func:`make_params` (``dx``, ``dy``, ``split``, ``storage``,
-    boundaries, ``gamma`` ... and an explicit ``dt``).
+    boundaries, ``gamma`` ... and an explicit ``dt``).  ``overlap`` recomputes
+    the next segment on a second stream during each reverse sweep, at the cost
+    of a second buffer of ``K - 1`` states (on a 256 x 256 grid the two streams
+    slow each other down: the reverse sweep's kernels already keep the memory
+    system busy).
     """
-    return _Rollout.apply(T0, tau_ref, Pr, rho0, ux0, uy0, int(nsteps), int(K), dict(params_kw))
+    return _Rollout.apply(T0, tau_ref, Pr, rho0, ux0, uy0, int(nsteps), int(K), bool(overlap), dict(params_kw))

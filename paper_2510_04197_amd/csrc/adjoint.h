@@ -94,62 +94,6 @@ __device__ inline void lim_partials(double a, double b, double beta, double& La,
   Lb = act ? (c1 ? 0.0 : (c2 ? 0.25 : 0.5 * beta)) : 0.0;
 }
 
-template <int BC>
-__device__ inline bool face_exists(int f, int n) {
-  return BC == BC_PERIODIC ? true : (f >= 0 && f <= n);
-}
-
-// Flux-part cotangent of one population along one axis for cell c.
-//   Xs[k]   = population at cell map(c - 3 + k), k = 0..6 (decoded);
-//   lam[k]  = lam' at cell map(c - 2 + k), k = 0..4;
-//   kv      = (dt / dx) v_alpha (non-zero); F(c) = ... - kv (face(c+1) - face(c)).
-// Face f lies between cells f-1 and f; with v > 0 its inputs are f-2, f-1, f
-// and the faces that read cell c are c, c+1, c+2 (c in slots 2, 1, 0); with
-// v < 0 the inputs are f-1, f, f+1 and the faces are c-1, c, c+1.  Under the
-// zero-gradient rule the ghost inputs are copies of the edge cell, so at an
-// edge cell further slots of the same faces map to it.
-template <int BC>
-__device__ inline double flux_adjoint(const double* Xs, const double* lam, int c, int n, double kv, double beta) {
-  double acc = 0.0;
-  const int d0 = kv > 0.0 ? 0 : -1;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const int df = d0 + k;  // face f = c + df
-    const int f = c + df;
-    if (BC != BC_PERIODIC && (f < 0 || f > n)) continue;
-    // dL/dface(f) = kv (lam'(f) - lam'(f-1)); cells outside a zero-gradient domain carry no lam'
-    const double lr = (BC == BC_PERIODIC || f <= n - 1) ? lam[df + 2] : 0.0;
-    const double ll = (BC == BC_PERIODIC || f >= 1) ? lam[df + 1] : 0.0;
-    const double gface = kv * (lr - ll);
-    const int q0 = kv > 0.0 ? df - 2 : df - 1;  // first input of face f, relative to c
-    const double X0 = Xs[q0 + 3], X1 = Xs[q0 + 4], X2 = Xs[q0 + 5];
-    double La, Lb, p0, p1, p2;
-    if (kv > 0.0) {
-      lim_partials(X1 - X0, X2 - X1, beta, La, Lb);
-      p0 = -La;
-      p1 = 1.0 + La - Lb;
-      p2 = Lb;
-    } else {
-      lim_partials(X1 - X2, X0 - X1, beta, La, Lb);
-      p0 = Lb;
-      p1 = 1.0 + La - Lb;
-      p2 = -La;
-    }
-    const double ps[3] = {p0, p1, p2};
-#pragma unroll
-    for (int sl = 0; sl < 3; ++sl) {
-      const int q = c + q0 + sl;
-      bool hit;
-      if (BC == BC_PERIODIC)
-        hit = n > 6 ? q == c : wrap_any<BC>(q, n) == c;
-      else
-        hit = q == c || (c == 0 && q < 0) || (c == n - 1 && q >= n);
-      if (hit) acc += gface * ps[sl];
-    }
-  }
-  return acc;
-}
-
 // ------------------------------------------------------------ reverse mode of the coefficient map
 // Gradient of  phi = sum_pq muf[p][q] bf[p][q] + sum_pq mug[p][q] bg[p][q] - s om1
 // (bf, bg, om1 as computed by collision_coeffs from the moments m and the
@@ -395,7 +339,8 @@ __device__ inline void coeffs_vjp(const NodeMoments& m, const KParams& kp, doubl
 //          mbar_r and 1 - om1 into a work array work[r][cell] (r = 0..12
 //          moments, 13: 1 - om1) and accumulates its share of d/dtau_ref,
 //          d/dPr;
-//   flux:  one wave per (population plane, row, strip of cells) assembles
+//   flux:  one wave per (group of population planes, strip of cells, range
+//          of rows) assembles, row after row,
 //          lam(c) = (1 - om1) lam'(c) + sum_r mbar_r dm_r/dX + flux cotangent.
 constexpr int ADJ_WORK_ROWS = N_MOMENTS + 1;
 
@@ -511,86 +456,164 @@ __device__ inline double lane_next_d(double v) {
 // lanes at each end supply the x stencil (radius 3) of their neighbours.
 constexpr int ADJ_STRIP = 58;
 
-// lam for plane pl, row y, strip x0 (one wave): the relaxation part from
-// the work array plus the flux cotangent.  The x stencil comes from the
-// neighbouring lanes, the y stencil from memory.
-template <int SPLIT, class S, int BCX, int BCY>
-__device__ inline void strip_adjoint_flux(const typename S::T* __restrict__ state, const double* __restrict__ lam1,
+// ------------------------------------------------------------ flux adjoint, row sweep
+// One wave takes the N1 planes (d, a, b), b = 0 .. N1-1, of one distribution
+// d and one abscissa xi_a, a strip of ADJ_STRIP columns and the rows
+// [ya, yb), and walks the rows upwards.  Along x, lane l forms the face
+// between the columns x-1 and x of the row once, and its three partials
+// reach their cells through lane shifts.  Along y every face is formed once.  At row c the wave forms face c+2
+// (xi_b > 0) or face c+1 (xi_b < 0); in both cases its three inputs are the
+// rows c, c+1, c+2 and its three partials belong to the rows c, c+1, c+2, so
+// the shares of the rows c+1 and c+2 are carried to the next rows (p1, p2).
+// The walk starts two rows early, at ya - 2, to collect the shares of the
+// faces below ya.  Under the zero-gradient rule the rows outside the domain
+// are copies of the edge rows and carry no lam': their shares (the rows
+// -2, -1 and ny, ny+1) go to the edge rows.  A ring of four rows per plane
+// holds X and lam' of the rows c .. c+3 (row c+3 in flight).
+// The relaxation part comes from the work array, read once per row for all
+// N1 planes: with xi_a fixed the Hermite polynomial of the moment cotangents
+// is a cubic (f) or linear (g) polynomial in xi_b.
+template <int SPLIT, class S, int BCX, int BCY, int D>
+__device__ inline void sweep_adjoint_flux(const typename S::T* __restrict__ state, const double* __restrict__ lam1,
                                           const double* __restrict__ work, double* __restrict__ lam0,
-                                          const KParams& kp, int pl, int x0, int y) {
+                                          const KParams& kp, int a, int x0, int ya, int yb) {
   constexpr int N1 = Set<SPLIT>::N1;
   constexpr int Q = Set<SPLIT>::Q;
+  constexpr bool ZGY = BCY != BC_PERIODIC;
   using L = GH<N1>;
   const int64_t cells = int64_t(kp.nx) * kp.ny;
   const int lane = threadIdx.x & 63;
   const int x = x0 - 3 + lane;
   const bool own = lane >= 3 && lane < 61 && x < kp.nx;
   const int gx = wrap_any<BCX>(x, kp.nx);
-  const int d = pl / Q, i = pl % Q;
-  const double xa = L::xi(i / N1), xb = L::xi(i % N1);
-  const double* lp = lam1 + int64_t(pl) * cells;
+  const double xa = L::xi(a);
   const double beta = 0.5 * kp.beta2;
-  double out = 0.0;
-  if (xa != 0.0) {  // plane-uniform: every lane takes part in the lane shifts
-    // lane l forms face f = x (between x-1 and x) once: G_s = dL/dface * dface/d(input s)
-    const double kv = kp.kx * xa;
-    const double Xc = adj_X<SPLIT, S>(state, kp, d, i, y, gx);
-    const double lc = lp[int64_t(y) * kp.nx + gx];
-    const double Xm1 = lane_prev_d(Xc), lm1 = lane_prev_d(lc);
-    const bool face_ok = BCX == BC_PERIODIC || (x >= 0 && x <= kp.nx);
-    const double lr = (BCX == BC_PERIODIC || x <= kp.nx - 1) ? lc : 0.0;
-    const double ll = (BCX == BC_PERIODIC || x >= 1) ? lm1 : 0.0;
-    const double gface = face_ok ? kv * (lr - ll) : 0.0;
-    double La, Lb, G0, G1, G2;
-    if (kv > 0.0) {  // inputs x-2, x-1, x
-      const double Xm2 = lane_prev_d(Xm1);
-      lim_partials(Xm1 - Xm2, Xc - Xm1, beta, La, Lb);
-      G0 = -La * gface;
-      G1 = (1.0 + La - Lb) * gface;
-      G2 = Lb * gface;
-    } else {  // inputs x-1, x, x+1
-      const double Xp1 = lane_next_d(Xc);
-      lim_partials(Xc - Xp1, Xm1 - Xc, beta, La, Lb);
-      G0 = Lb * gface;
-      G1 = (1.0 + La - Lb) * gface;
-      G2 = -La * gface;
-    }
-    // cell x gathers slot 2 of face x, 1 of x+1, 0 of x+2 (v > 0) or
-    // slot 2 of face x-1, 1 of x, 0 of x+1 (v < 0)
-    double gx_sum;
-    if (kv > 0.0)
-      gx_sum = G2 + lane_next_d(G1) + lane_next_d(lane_next_d(G0));
-    else
-      gx_sum = lane_prev_d(G2) + G1 + lane_next_d(G0);
-    if (BCX != BC_PERIODIC) {
-      // ghost cells (copies of the edge cells) hand their share to the edge cell
-      const double a1 = lane_prev_d(gx_sum), a2 = lane_prev_d(a1), b1 = lane_next_d(gx_sum), b2 = lane_next_d(b1);
-      if (x == 0) gx_sum += a1 + a2;
-      if (x == kp.nx - 1) gx_sum += b1 + b2;
-    }
-    out += gx_sum;
-  }
-  if (!own) return;
-  if (xb != 0.0) {
-    double Xs[7], lm[5];
+  const double kvx = kp.kx * xa;
+  const int pl0 = D * Q + a * N1;
+  const double* lp = lam1 + int64_t(pl0) * cells + gx;
+
+  constexpr int NW = D == 0 ? 11 : 4;  // work rows read: 0..9 and 13 (f), 10..13 (g)
+  double X[N1][4], Lm[N1][4], p1[N1], p2[N1], gs[N1];
+  double zf[4];  // 1 inside the domain, 0 for the rows outside (zero-gradient)
 #pragma unroll
-    for (int k = 0; k < 7; ++k) Xs[k] = adj_X<SPLIT, S>(state, kp, d, i, wrap<BCY>(y - 3 + k, kp.ny), x);
+  for (int b = 0; b < N1; ++b) p1[b] = p2[b] = gs[b] = 0.0;
+
+  auto fill = [&](auto slot, int r) {
+    constexpr int s = decltype(slot)::value;
+    const int ry = wrap<BCY>(r, kp.ny);
+    zf[s] = (!ZGY || (r >= 0 && r < kp.ny)) ? 1.0 : 0.0;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) lm[k] = lp[int64_t(wrap<BCY>(y - 2 + k, kp.ny)) * kp.nx + x];
-    out += flux_adjoint<BCY>(Xs, lm, y, kp.ny, kp.ky * xb, beta);
+    for (int b = 0; b < N1; ++b) {
+      X[b][s] = adj_X<SPLIT, S>(state, kp, D, a * N1 + b, ry, gx);
+      Lm[b][s] = lp[int64_t(b) * cells + int64_t(ry) * kp.nx];
+    }
+  };
+
+  auto step = [&](auto phase, int c) {
+    constexpr int P = decltype(phase)::value;
+    constexpr int s0 = P, s1 = (P + 1) & 3, s2 = (P + 2) & 3, s3 = (P + 3) & 3;
+    if (c + 3 <= yb + 1) fill(std::integral_constant<int, s3>(), c + 3);
+    const bool outrow = c >= ya;
+    // relaxation part: moment cotangents of the cell (row c)
+    double w[NW];
+    if (outrow) {
+      const int64_t cc = int64_t(c) * kp.nx + gx;
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        const int r = D == 0 ? (k < 10 ? k : N_MOMENTS) : (k < 3 ? 10 + k : N_MOMENTS);
+        w[k] = work[int64_t(r) * cells + cc];
+      }
+    }
+    const bool last = ZGY && c == kp.ny - 1;
+#pragma unroll
+    for (int b = 0; b < N1; ++b) {
+      const double xb = L::xi(b);
+      // y: the face of this row and the carried shares
+      double oy = 0.0;
+      if (xb != 0.0) {
+        const double kv = kp.ky * xb;
+        const double X0 = X[b][s0], X1 = X[b][s1], X2 = X[b][s2];
+        double La, Lb, G0, G1, G2;
+        if (xb > 0.0) {  // face c+2: inputs c, c+1, c+2; dL/dface = kv (lam'(c+2) - lam'(c+1))
+          const double g = kv * (zf[s2] * Lm[b][s2] - zf[s1] * Lm[b][s1]);
+          lim_partials(X1 - X0, X2 - X1, beta, La, Lb);
+          G0 = -La * g;
+          G1 = (1.0 + La - Lb) * g;
+          G2 = Lb * g;
+        } else {  // face c+1: inputs c, c+1, c+2; dL/dface = kv (lam'(c+1) - lam'(c))
+          const double g = kv * (zf[s1] * Lm[b][s1] - zf[s0] * Lm[b][s0]);
+          lim_partials(X1 - X2, X0 - X1, beta, La, Lb);
+          G0 = Lb * g;
+          G1 = (1.0 + La - Lb) * g;
+          G2 = -La * g;
+        }
+        oy = p1[b] + G0;
+        p1[b] = p2[b] + G1;
+        p2[b] = G2;
+        if (last) oy += p1[b] + p2[b];  // shares of the rows ny, ny+1
+      }
+      if (!outrow) {
+        if (ZGY) gs[b] += oy;  // shares of the rows -2, -1 (used when ya == 0)
+        continue;
+      }
+      double out = oy;
+      if (ZGY && c == 0) out += gs[b];
+      // x: lane l forms face x (between x-1 and x) of row c
+      if (kvx != 0.0) {
+        const double Xc = X[b][s0], lc = Lm[b][s0];
+        const double Xm1 = lane_prev_d(Xc), lm1 = lane_prev_d(lc);
+        const bool face_ok = BCX == BC_PERIODIC || (x >= 0 && x <= kp.nx);
+        const double lr = (BCX == BC_PERIODIC || x <= kp.nx - 1) ? lc : 0.0;
+        const double ll = (BCX == BC_PERIODIC || x >= 1) ? lm1 : 0.0;
+        const double gface = face_ok ? kvx * (lr - ll) : 0.0;
+        double La, Lb, gsum;
+        if (kvx > 0.0) {  // inputs x-2, x-1, x; cell x takes slot 2 of face x, 1 of x+1, 0 of x+2
+          const double Xm2 = lane_prev_d(Xm1);
+          lim_partials(Xm1 - Xm2, Xc - Xm1, beta, La, Lb);
+          const double G0 = -La * gface, G1 = (1.0 + La - Lb) * gface, G2 = Lb * gface;
+          gsum = G2 + lane_next_d(G1) + lane_next_d(lane_next_d(G0));
+        } else {  // inputs x-1, x, x+1; cell x takes slot 2 of face x-1, 1 of x, 0 of x+1
+          const double Xp1 = lane_next_d(Xc);
+          lim_partials(Xc - Xp1, Xm1 - Xc, beta, La, Lb);
+          const double G0 = Lb * gface, G1 = (1.0 + La - Lb) * gface, G2 = -La * gface;
+          gsum = lane_prev_d(G2) + G1 + lane_next_d(G0);
+        }
+        if (BCX != BC_PERIODIC) {
+          // ghost columns (copies of the edge columns) hand their share to the edge column
+          const double a1 = lane_prev_d(gsum), a2 = lane_prev_d(a1), b1 = lane_next_d(gsum), b2 = lane_next_d(b1);
+          if (x == 0) gsum += a1 + a2;
+          if (x == kp.nx - 1) gsum += b1 + b2;
+        }
+        out += gsum;
+      }
+      // relaxation: (1 - om1) lam' + sum_r mbar_r dm_r/dX
+      if constexpr (D == 0) {
+        const double xa2 = xa * xa;
+        const double A0 = w[0] + w[1] * xa + w[3] * xa2 + w[6] * (xa2 * xa);
+        const double A1 = w[2] + w[4] * xa + w[7] * xa2;
+        const double A2 = w[5] + w[8] * xa;
+        out += A0 + xb * (A1 + xb * (A2 + xb * w[9])) + w[10] * Lm[b][s0];
+      } else {
+        out += w[0] + w[1] * xa + w[2] * xb + w[3] * Lm[b][s0];
+      }
+      if (own) lam0[int64_t(pl0 + b) * cells + int64_t(c) * kp.nx + x] = out;
+    }
+  };
+
+  int c = ya - 2;
+  fill(std::integral_constant<int, 0>(), c);
+  fill(std::integral_constant<int, 1>(), c + 1);
+  fill(std::integral_constant<int, 2>(), c + 2);
+  for (;;) {
+    step(std::integral_constant<int, 0>(), c);
+    if (++c >= yb) break;
+    step(std::integral_constant<int, 1>(), c);
+    if (++c >= yb) break;
+    step(std::integral_constant<int, 2>(), c);
+    if (++c >= yb) break;
+    step(std::integral_constant<int, 3>(), c);
+    if (++c >= yb) break;
   }
-  // relaxation part: (1 - om1) lam' + sum_r mbar_r dm_r/dX
-  const int64_t c = int64_t(y) * kp.nx + x;
-  auto mb = [&](int r) { return work[int64_t(r) * cells + c]; };
-  out += mb(N_MOMENTS) * lp[c];
-  if (d == 0) {
-    const double xa2 = xa * xa, xb2 = xb * xb;
-    out += mb(0) + mb(1) * xa + mb(2) * xb + mb(3) * xa2 + mb(4) * (xa * xb) + mb(5) * xb2 + mb(6) * (xa2 * xa) +
-           mb(7) * (xa2 * xb) + mb(8) * (xa * xb2) + mb(9) * (xb2 * xb);
-  } else {
-    out += mb(10) + mb(11) * xa + mb(12) * xb;
-  }
-  lam0[int64_t(pl) * cells + c] = out;
 }
 
 // ------------------------------------------------------------ readout adjoint

@@ -371,19 +371,36 @@ __global__ __launch_bounds__(RED_THREADS) void k_adjoint_relax(const typename S:
   }
 }
 
-// Adjoint step, flux part: blockIdx.x is the strip of ADJ_STRIP cells,
-// blockIdx.z the population plane; the 4 waves of a block take rows
-// 4 blockIdx.y + w, grid-stride along y.
+// Adjoint step, flux part: four waves per workgroup; workgroups are dealt
+// so that every XCD gets one contiguous range of waves.  Wave w takes the
+// plane group w % (2 N1) (distribution d, abscissa xi_a), the strip
+// (w / 2 N1) % nstrips and the row range ch * (w / (2 N1 nstrips)), so the
+// 2 N1 groups of the same cells share the work rows in one L2.
+#ifndef DVBM_ADJ_WAVES
+#define DVBM_ADJ_WAVES 4096  // waves the flux-adjoint launch aims for
+#endif
+#ifndef DVBM_ADJ_CH_MIN
+#define DVBM_ADJ_CH_MIN 8  // fewest rows per wave (each range walks two rows more)
+#endif
 template <int SPLIT, class S, int BCX, int BCY>
 __global__ __launch_bounds__(256) void k_adjoint_flux(const typename S::T* __restrict__ state,
                                                       const double* __restrict__ lam1,
                                                       const double* __restrict__ work, double* __restrict__ lam0,
-                                                      KParams kp) {
-  const int w = threadIdx.x / 64;
-  for (int y = 4 * blockIdx.y + w; y < kp.ny; y += 4 * gridDim.y)
-    strip_adjoint_flux<SPLIT, S, BCX, BCY>(state, lam1, work, lam0, kp, int(blockIdx.z), blockIdx.x * ADJ_STRIP, y);
+                                                      KParams kp, int nstrips, int ch, int nchunks) {
+  constexpr int N1 = Set<SPLIT>::N1;
+  const int nb = int(gridDim.x), blk = int(blockIdx.x);
+  const int xcd = blk % 8, k = blk / 8, base = nb / 8, rem = nb % 8;
+  const int lb = xcd < rem ? xcd * (base + 1) + k : rem * (base + 1) + (xcd - rem) * base + k;
+  const int w = lb * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x) / 64);
+  const int g = w % (2 * N1), rest = w / (2 * N1);
+  const int strip = rest % nstrips, chunk = rest / nstrips;
+  if (chunk >= nchunks) return;
+  const int ya = chunk * ch, yb = ya + ch < kp.ny ? ya + ch : kp.ny;
+  if (g < N1)
+    sweep_adjoint_flux<SPLIT, S, BCX, BCY, 0>(state, lam1, work, lam0, kp, g, strip * ADJ_STRIP, ya, yb);
+  else
+    sweep_adjoint_flux<SPLIT, S, BCX, BCY, 1>(state, lam1, work, lam0, kp, g - N1, strip * ADJ_STRIP, ya, yb);
 }
-
 
 template <int SPLIT, class S>
 __global__ __launch_bounds__(256) void k_adjoint_readout(const typename S::T* __restrict__ state,
@@ -664,10 +681,12 @@ void adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, dou
                          h->ws, ticket, dparams);
       break;
   }
-  const int ry = (h->p.ny + 3) / 4;
-  const dim3 fgrid((h->p.nx + ADJ_STRIP - 1) / ADJ_STRIP, ry < 65535 ? ry : 65535, 2 * Set<SPLIT>::Q);
-  hipLaunchKernelGGL((k_adjoint_flux<SPLIT, S, BCX, BCY>), fgrid, dim3(256), 0, h->stream, s, lam1, work, lam0,
-                     h->kp);
+  const int64_t groups = 2 * Set<SPLIT>::N1, nstrips = (h->p.nx + ADJ_STRIP - 1) / ADJ_STRIP;
+  int64_t ch = (int64_t(h->p.ny) * groups * nstrips + DVBM_ADJ_WAVES - 1) / DVBM_ADJ_WAVES;
+  ch = ch < DVBM_ADJ_CH_MIN ? DVBM_ADJ_CH_MIN : (ch > h->p.ny ? h->p.ny : ch);
+  const int64_t nchunks = (h->p.ny + ch - 1) / ch, waves = groups * nstrips * nchunks;
+  hipLaunchKernelGGL((k_adjoint_flux<SPLIT, S, BCX, BCY>), dim3(unsigned((waves + 3) / 4)), dim3(256), 0, h->stream,
+                     s, lam1, work, lam0, h->kp, int(nstrips), int(ch), int(nchunks));
 }
 
 }  // namespace dvbm_launch
