@@ -282,6 +282,35 @@ def test_thermal_wave_4096_sampled(storage, tol):
     assert rel(got, ref) < tol
 
 
+def test_largest_grids_sampled():
+    """6528 x 6528, split II.  In float32 one distribution takes 3.97 GiB: the
+    32-bit buffer offsets are near their 4 GiB limit, and the grid is above the
+    column-sweep kernel's 2 GiB, so AUTO takes the per-cell kernel.  In bfloat16
+    it takes 1.98 GiB, just below the column-sweep kernel's limit, which AUTO
+    then takes."""
+    n = 6528
+    print(f"[largest grids] {n}x{n}", flush=True)
+    wl = smooth_random(n, n, seed=21, amp_T=0.05)
+    for storage in ("f32", "bf16_dev"):
+        print(f"[largest grids] {storage}", flush=True)
+        s, p = solver(wl, split=2, storage=storage, Pr=0.71, tau_ref=5e-5)
+        assert s.buffers[0].numel() // 2 == 25 * n * n * (4 if storage == "f32" else 2)
+        got, ref, _ = sampled_check(s, p, nsamples=48, seed=5)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        if storage == "f32":
+            assert rel(got, ref) < 1e-5
+        else:
+            # the rounding of the stored deviation from w_i (f) bounds the error
+            w = O.velocity_set(oracle_cfg(p))[1].reshape(-1, 1)
+            dev_f = torch.linalg.vector_norm(ref[0] - w)
+            assert float(torch.linalg.vector_norm(got[0] - ref[0])) <= 1.5 * 2.0 ** -8 * float(dev_f) + \
+                1e-6 * float(torch.linalg.vector_norm(ref[0]))
+            assert float(torch.linalg.vector_norm(got[1] - ref[1])) <= 1.5 * 2.0 ** -8 * float(
+                torch.linalg.vector_norm(ref[1]))
+
+
 # ---------------------------------------------------------------- errors raised from device checks
 def test_nonphysical_initial_state_rejected():
     wl = smooth_random(16, 16, seed=1)
