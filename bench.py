@@ -76,11 +76,12 @@ def traffic_entry(kernel_key: str):
 
 def step_kernel_name(storage: str, wl) -> str:
     """The step kernel the library launches for this storage and grid size."""
+    big = wl.nx * wl.ny >= 3 << 18
     if storage == "f64":
-        return "k_collide_advect_lds"
+        return "k_collide_advect_sweep" if big else "k_collide_advect_lds"
     pitch = (wl.nx + 63) // 64 * 64
     Q = 25
-    if wl.nx * wl.ny >= 3 << 18 and pitch * wl.ny * Q * STORAGE_BYTES[storage] <= 1 << 31:
+    if big and pitch * wl.ny * Q * STORAGE_BYTES[storage] <= 1 << 31:
         return "k_collide_advect_sweep"
     return "k_collide_advect"
 

@@ -63,10 +63,10 @@ enum dvbm_storage { DVBM_F64 = 0, DVBM_F32 = 1, DVBM_BF16_DEV = 2, DVBM_FP16_DEV
 enum dvbm_bc { DVBM_PERIODIC = 0, DVBM_ZERO_GRADIENT = 1 };
 enum dvbm_visc { DVBM_CONST_MU = 0, DVBM_CONST_TAU = 1 };
 /* Step kernel (all compute the same update; the choice only affects speed):
- * AUTO picks the LDS tile kernel for DVBM_F64 and, for the other storages,
- * the column sweep on grids of at least 3 * 2^18 cells whose distribution
- * fits 2 GiB, else the per-cell kernel.  SWEEP requires 32/16-bit storage
- * and a distribution of at most 2 GiB. */
+ * AUTO picks the column sweep on grids of at least 3 * 2^18 cells (for
+ * 32/16-bit storage only when one distribution fits 2 GiB), else the LDS
+ * tile kernel for DVBM_F64 and the per-cell kernel for the other storages.
+ * SWEEP with 32/16-bit storage requires a distribution of at most 2 GiB. */
 enum dvbm_kernel { DVBM_KERNEL_AUTO = 0, DVBM_KERNEL_CELL = 1, DVBM_KERNEL_SWEEP = 2, DVBM_KERNEL_TILE = 3 };
 
 /*

@@ -121,11 +121,13 @@ __device__ inline void sweep_range(int ny, int kseg, int j, int& ya, int& yb) {
   yb = ya + len;
 }
 
-// Column sweep (32/16-bit storage): workgroups of 2 SWEEP_K waves, wave w
-// advancing distribution w / SWEEP_K (0: f, 1: g) of strip
-// sg * SWEEP_K + w % SWEEP_K; workgroup b is logical (strip group, row range)
-// L, dealt so that every XCD gets one contiguous range of L;
-// L = j * ngroups + sg covers strip group sg, row range j.
+// Column sweep: workgroups of 2 K waves, wave w advancing distribution
+// w / K (0: f, 1: g) of strip sg * K + w % K; workgroup b is logical (strip
+// group, row range) L, dealt so that every XCD gets one contiguous range of
+// L; L = j * ngroups + sg covers strip group sg, row range j.  K is 4 for
+// 32/16-bit storage (two waves per SIMD).  Float64 windows need about 370
+// registers, so float64 storage runs one wave per SIMD and K = 2: the same
+// bytes in flight per CU.
 #ifndef DVBM_SWEEP_WPE
 #define DVBM_SWEEP_WPE 2
 #endif
@@ -133,10 +135,25 @@ __device__ inline void sweep_range(int ny, int kseg, int j, int& ya, int& yb) {
 // occupy the device, and the per-cell kernel is faster (measured: 256^2 and
 // 512^2 favour it, 1024^2 and larger the sweep).
 constexpr int64_t SWEEP_MIN_CELLS = 3 << 18;
+#ifndef DVBM_SWEEP_K64
+#define DVBM_SWEEP_K64 2  // strips per workgroup, float64 storage
+#endif
+#ifndef DVBM_SWEEP_WPE64
+#define DVBM_SWEEP_WPE64 1
+#endif
+template <class S>
+constexpr int sweep_k() {
+  return sizeof(typename S::T) == 8 ? DVBM_SWEEP_K64 : SWEEP_K;
+}
+template <class S>
+constexpr int sweep_wpe() {
+  return sizeof(typename S::T) == 8 ? DVBM_SWEEP_WPE64 : DVBM_SWEEP_WPE;
+}
 template <int SPLIT, class S, int BCX, int BCY, int PRM>
-__global__ __launch_bounds__(128 * SWEEP_K) __attribute__((amdgpu_waves_per_eu(DVBM_SWEEP_WPE))) void
+__global__ __launch_bounds__(128 * sweep_k<S>()) __attribute__((amdgpu_waves_per_eu(sweep_wpe<S>()))) void
 k_collide_advect_sweep(const typename S::T* __restrict__ src, typename S::T* __restrict__ dst, KParams kp,
                        int ngroups, int kseg) {
+  constexpr int SWEEP_K = sweep_k<S>();
   __shared__ SweepShared sh[SWEEP_K];
   const int total = ngroups * kseg;
   const int per = (total + 7) / 8;
@@ -499,8 +516,8 @@ std::string check_params(const dvbm_params* p) {
   const double pitch = double((int64_t(p->nx) + 63) / 64 * 64);
   const double dist = pitch * double(p->ny) * storage_bytes(p->storage) * (p->split == 1 ? 16 : 25);
   if (dist > 4294967295.0) return "one distribution (Q * ny * pitch elements) must be smaller than 4 GiB";
-  if (p->kernel == DVBM_KERNEL_SWEEP && (p->storage == DVBM_F64 || dist > 2147483648.0))
-    return "the column-sweep kernel needs 32/16-bit storage and a distribution of at most 2 GiB";
+  if (p->kernel == DVBM_KERNEL_SWEEP && p->storage != DVBM_F64 && dist > 2147483648.0)
+    return "the column-sweep kernel needs a distribution of at most 2 GiB for 32/16-bit storage";
   return "";
 }
 
@@ -552,11 +569,11 @@ KParams make_kparams(const dvbm_params& p, double dt) {
 // Row ranges per strip group for the column sweep: as many workgroups as
 // the device holds at once (one per strip group and range), but ranges of
 // at least 8 rows so that the 4 warm-up rows of a range stay a minor cost.
-int sweep_ranges(const void* kern, int ngroups, int ny) {
+int sweep_ranges(const void* kern, int block, int ngroups, int ny) {
   int dev = 0, ncu = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 128 * SWEEP_K, 0) != hipSuccess || ncu <= 0 || per_cu <= 0) {
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, 0) != hipSuccess || ncu <= 0 || per_cu <= 0) {
     (void)hipGetLastError();
     ncu = 256;
     per_cu = 1;
@@ -579,9 +596,10 @@ namespace dvbm_launch {
 // The kernel a handle's steps use (the AUTO rule of dvbm_kernel).
 inline int step_kernel(const dvbm_handle* h) {
   if (h->p.kernel != DVBM_KERNEL_AUTO) return h->p.kernel;
-  if (h->p.storage == DVBM_F64) return DVBM_KERNEL_TILE;
+  const bool big = int64_t(h->p.nx) * h->p.ny >= SWEEP_MIN_CELLS;
+  if (h->p.storage == DVBM_F64) return DVBM_SWEEP && big ? DVBM_KERNEL_SWEEP : DVBM_KERNEL_TILE;
   const uint64_t dist = uint64_t(h->kp.plane) * h->Q * uint64_t(storage_bytes(h->p.storage));
-  if (DVBM_SWEEP && int64_t(h->p.nx) * h->p.ny >= SWEEP_MIN_CELLS && dist <= (uint64_t(1) << 31))
+  if (DVBM_SWEEP && big && dist <= (uint64_t(1) << 31))
     return DVBM_KERNEL_SWEEP;
   return DVBM_KERNEL_CELL;
 }
@@ -598,12 +616,13 @@ void launch_step_pr(const dvbm_handle* h, const void* src, void* dst) {
                        s, d, h->kp);
     return;
   }
-  if constexpr (sizeof(T) < 8) {
+  {
+    constexpr int SWEEP_K = sweep_k<S>();
     if (kern_id == DVBM_KERNEL_SWEEP) {
       const auto kern = k_collide_advect_sweep<SPLIT, S, BCX, BCY, PRM>;
       const int nstrips = (h->p.nx + SWEEP_OWN - 1) / SWEEP_OWN;
       const int ngroups = (nstrips + SWEEP_K - 1) / SWEEP_K;
-      if (h->sweep_kseg == 0) h->sweep_kseg = sweep_ranges(reinterpret_cast<const void*>(kern), ngroups, h->p.ny);
+      if (h->sweep_kseg == 0) h->sweep_kseg = sweep_ranges(reinterpret_cast<const void*>(kern), 128 * SWEEP_K, ngroups, h->p.ny);
       const int total = ngroups * h->sweep_kseg;
       const dim3 grid(8 * ((total + 7) / 8));
       hipLaunchKernelGGL(kern, grid, dim3(128 * SWEEP_K), 0, h->stream, s, d, h->kp, ngroups, h->sweep_kseg);

@@ -46,6 +46,14 @@ __device__ inline rsrc_t dist_rsrc(const void* base, int d, uint32_t dist_bytes)
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(p), 0, dist_bytes, RSRC_WORD3);
 }
 
+// One population plane (index pl of 2Q) as its own buffer resource: the
+// stencil-only lanes of the column sweep store to offset 2^31, beyond any
+// plane, and the row offset plus 2^31 stays below 2^32.
+__device__ inline rsrc_t plane_rsrc(const void* base, int pl, uint32_t plane_bytes) {
+  const char* p = static_cast<const char*>(base) + size_t(pl) * size_t(plane_bytes);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(p), 0, plane_bytes, RSRC_WORD3);
+}
+
 template <class T>
 struct Buf;
 template <>

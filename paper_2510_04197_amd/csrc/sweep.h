@@ -1,5 +1,5 @@
-// Column-sweep form of the fused DDF-QE DVBM step for 32-bit and 16-bit
-// storage (float32 arithmetic).
+// Column-sweep form of the fused DDF-QE DVBM step (float32 arithmetic for
+// 32-bit and 16-bit storage, float64 for float64 storage).
 //
 // A workgroup of two waves owns a strip of SWEEP_OWN columns and walks a
 // range of rows in +y; one wave advances f, the other g.  The 64 lanes of a
@@ -17,11 +17,17 @@ namespace dvbm {
 
 constexpr int SWEEP_OWN = 60;  // cells per strip: 64 lanes minus 2 stencil lanes on each side
 
-// A loaded value kept in a float32 register as its stored bit pattern (the
-// 16-bit formats zero-extended), so that the decode, and with it the wait for
-// the load, happens at the value's first use rather than right after the load.
+// A loaded value kept in a register as its stored bit pattern (the 16-bit
+// formats zero-extended into a float32 register), so that the decode, and
+// with it the wait for the load, happens at the value's first use rather than
+// right after the load.
 template <class T>
 struct Bits;
+template <>
+struct Bits<double> {
+  __device__ static double keep(double v) { return v; }
+  __device__ static double decode(double b) { return b; }
+};
 template <>
 struct Bits<float> {
   __device__ static float keep(float v) { return v; }
@@ -46,6 +52,18 @@ __device__ inline float lane_prev(float v) {
 }
 __device__ inline float lane_next(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+}
+__device__ inline double lane_prev(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_mov_dpp(int(uint32_t(b)), 0x138, 0xf, 0xf, true);
+  const uint32_t hi = __builtin_amdgcn_mov_dpp(int(uint32_t(b >> 32)), 0x138, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+__device__ inline double lane_next(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_mov_dpp(int(uint32_t(b)), 0x130, 0xf, 0xf, true);
+  const uint32_t hi = __builtin_amdgcn_mov_dpp(int(uint32_t(b >> 32)), 0x130, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
 }
 
 // Float64 moments (Eqs. eq_quadratur1-3, Table I notation) of one
@@ -139,7 +157,6 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
                                     const KParams& kp, int x0, int ya, int yb, SweepShared& sh) {
   using R = typename S::C;
   using T = typename S::T;
-  static_assert(sizeof(R) == 4, "the sweep computes in float32");
   constexpr int N1 = Set<SPLIT>::N1;
   constexpr int Q = Set<SPLIT>::Q;
   constexpr int N = D == 0 ? Set<SPLIT>::NF : 2;  // Grad order of this distribution
@@ -151,8 +168,10 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
   const bool own = lane >= 2 && lane < 62 && x < kp.nx;
   const uint32_t vo = uint32_t(wrap_any<BCX>(x, kp.nx)) * SZ;
   // stores of the stencil-only lanes go to offset 2^31, which the bounds
-  // check of the buffer resource (a distribution of at most 2^31 bytes)
-  // discards: every lane stores, so no branch splits the memory counters
+  // check of the buffer resource discards: every lane stores, so no branch
+  // splits the memory counters.  The resource is the distribution (at most
+  // 2^31 bytes) for 32/16-bit storage and the plane for float64 storage,
+  // whose distributions can exceed 2^31 bytes
   const uint32_t vo_st = own ? vo : 0x80000000u;
   const uint32_t row_bytes = uint32_t(kp.pitch) * SZ;
   const uint32_t plane_bytes = uint32_t(kp.plane) * SZ;
@@ -313,6 +332,8 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
         xn -= div;  // stored values and deviations share the flux form (L is homogeneous)
         if constexpr (S::dev)
           Buf<T>::st(rsrc_dst, uint32_t(i) * plane_bytes + r_st, vo_st, S::enc_dev(xn));
+        else if constexpr (sizeof(T) == 8)
+          Buf<T>::st(plane_rsrc(dst, D * Q + i, plane_bytes), r_st, vo_st, S::enc(xn, R(1), R(0)));
         else
           Buf<T>::st(rsrc_dst, uint32_t(i) * plane_bytes + r_st, vo_st, S::enc(xn, R(1), R(0)));
         // the window drops its first row; that register receives the row it now needs

@@ -61,7 +61,7 @@ def test_initial_equilibrium(split, storage, tol):
 CASES = [(split, Pr, bc) for split in (1, 2) for Pr in (0.5, 1.0, 2.0) for bc in ("periodic", "zero_gradient")]
 
 
-@pytest.mark.parametrize("kernel", ("tile", "cell"))
+@pytest.mark.parametrize("kernel", ("tile", "cell", "sweep"))
 @pytest.mark.parametrize("split,Pr,bc", CASES)
 def test_steps_fp64(split, Pr, bc, kernel):
     wl = smooth_random(70, 37, seed=2)  # two 64-wide tiles in x with a ragged tail, ragged rows in y
@@ -169,8 +169,6 @@ def test_periodic_conservation_fp64(split, Pr):
 def test_uniform_state_fixed_point_all_storages(kernel):
     wl = uniform(70, 12, rho=1.1, ux=0.3, uy=-0.1, T=1.05)
     for storage in ("f64", "f32", "bf16_dev", "fp16_dev"):
-        if kernel == "sweep" and storage == "f64":
-            continue
         s, _ = solver(wl, split=2, storage=storage, tau_ref=0.02, cfl=0.1, kernel=kernel)
         X0 = s.store_populations()
         s.step(10)
@@ -184,18 +182,20 @@ def test_uniform_state_fixed_point_all_storages(kernel):
 # ---------------------------------------------------------------- column-sweep geometry
 @pytest.mark.parametrize("nx,ny", ((4, 4), (59, 5), (60, 7), (61, 40), (241, 13), (250, 9), (480, 6)))
 @pytest.mark.parametrize("bc", ("periodic", "zero_gradient"))
-def test_sweep_strips_and_row_ranges_fp32(nx, ny, bc):
-    """Strips of 60 columns in groups of 4 (empty strips at the end of the last group), row ranges of 3 m rows
-    with the last one overlapping its predecessor, grids narrower than a strip."""
+@pytest.mark.parametrize("storage", ("f32", "f64"))
+def test_sweep_strips_and_row_ranges(nx, ny, bc, storage):
+    """Strips of 60 columns in groups of 4 (float32) or 2 (float64), with empty strips at the end of the last
+    group, row ranges of 3 m rows with the last one overlapping its predecessor, grids narrower than a strip."""
     wl = smooth_random(nx, ny, seed=31, amp_T=0.05)
-    s, p = solver(wl, split=2, storage="f32", Pr=0.6, tau_ref=0.02, bc_x=bc, bc_y=bc, cfl=0.1, kernel="sweep")
+    s, p = solver(wl, split=2, storage=storage, Pr=0.6, tau_ref=0.02, bc_x=bc, bc_y=bc, cfl=0.1, kernel="sweep")
     cfg = oracle_cfg(p)
     f0, g0 = O.initial_state(wl.rho, wl.ux, wl.uy, wl.T, cfg)
     s.step(4)
     f, g = oracle_state(s)
     fo, go = O.run(f0, g0, cfg, s.dt, 4)
-    assert rel(f, fo) < 1e-5 and rel(g, go) < 1e-5
-    assert rel(f - f0, fo - f0) < 1e-3 and rel(g - g0, go - g0) < 1e-3
+    tol, tol_inc = (1e-5, 1e-3) if storage == "f32" else (1e-12, 1e-9)
+    assert rel(f, fo) < tol and rel(g, go) < tol
+    assert rel(f - f0, fo - f0) < tol_inc and rel(g - g0, go - g0) < tol_inc
 
 
 # ---------------------------------------------------------------- 16-bit deviation storage
@@ -309,6 +309,20 @@ def test_largest_grids_sampled():
                 1e-6 * float(torch.linalg.vector_norm(ref[0]))
             assert float(torch.linalg.vector_norm(got[1] - ref[1])) <= 1.5 * 2.0 ** -8 * float(
                 torch.linalg.vector_norm(ref[1]))
+
+
+def test_largest_grid_fp64_sampled():
+    """4608 x 4608 in float64: one distribution takes 3.96 GiB, near the 4 GiB
+    limit of the 32-bit load offsets; AUTO takes the column sweep, whose stores
+    go through one buffer resource per plane."""
+    n = 4608
+    print(f"[largest grid fp64] {n}x{n}", flush=True)
+    wl = smooth_random(n, n, seed=22, amp_T=0.05)
+    s, p = solver(wl, split=2, storage="f64", Pr=0.71, tau_ref=5e-5)
+    assert s.buffers[0].numel() // 2 == 25 * n * n * 8
+    got, ref, before = sampled_check(s, p, nsamples=48, seed=6)
+    assert rel(got, ref) < 1e-12
+    assert rel(got - before, ref - before) < 1e-9
 
 
 # ---------------------------------------------------------------- errors raised from device checks
