@@ -566,10 +566,15 @@ KParams make_kparams(const dvbm_params& p, double dt) {
   return k;
 }
 
-// Row ranges per strip group for the column sweep: as many workgroups as
-// the device holds at once (one per strip group and range), but ranges of
-// at least 8 rows so that the 4 warm-up rows of a range stay a minor cost.
-int sweep_ranges(const void* kern, int block, int ngroups, int ny) {
+// Row ranges per strip group for the column sweep.  One workgroup fits a
+// CU at a time, so one round of ranges (as many workgroups as the device
+// holds) ends with its slowest CU; `rounds` rounds of shorter ranges let the
+// faster CUs take more of them.  Ranges keep at least 48 rows (the 4
+// warm-up rows of a range stay under 10 %), and never fewer ranges than one
+// round nor ranges shorter than 9 rows.  Measured on the 4096^2 thermal
+// wave: float64 storage gains 15 % at 6 rounds, float32 4.5 % at 4 rounds,
+// the 16-bit formats nothing.
+int sweep_ranges(const void* kern, int block, int ngroups, int ny, int rounds) {
   int dev = 0, ncu = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -578,8 +583,10 @@ int sweep_ranges(const void* kern, int block, int ngroups, int ny) {
     ncu = 256;
     per_cu = 1;
   }
-  const int cap = ncu * per_cu;
-  int want = cap / ngroups < ny / 9 ? cap / ngroups : ny / 9;
+  const int one = ncu * per_cu / ngroups;  // ranges per strip group in one round
+  int want = rounds * one < ny / 48 ? rounds * one : ny / 48;
+  if (want < one) want = one;
+  if (want > ny / 9) want = ny / 9;
   if (want < 1) want = 1;
   // the number of ranges of sweep_len rows that cover the column
   const int len = sweep_len(ny, want);
@@ -622,7 +629,8 @@ void launch_step_pr(const dvbm_handle* h, const void* src, void* dst) {
       const auto kern = k_collide_advect_sweep<SPLIT, S, BCX, BCY, PRM>;
       const int nstrips = (h->p.nx + SWEEP_OWN - 1) / SWEEP_OWN;
       const int ngroups = (nstrips + SWEEP_K - 1) / SWEEP_K;
-      if (h->sweep_kseg == 0) h->sweep_kseg = sweep_ranges(reinterpret_cast<const void*>(kern), 128 * SWEEP_K, ngroups, h->p.ny);
+      if (h->sweep_kseg == 0) h->sweep_kseg = sweep_ranges(reinterpret_cast<const void*>(kern), 128 * SWEEP_K, ngroups, h->p.ny,
+                                     sizeof(T) == 8 ? 6 : (sizeof(T) == 4 ? 4 : 1));
       const int total = ngroups * h->sweep_kseg;
       const dim3 grid(8 * ((total + 7) / 8));
       hipLaunchKernelGGL(kern, grid, dim3(128 * SWEEP_K), 0, h->stream, s, d, h->kp, ngroups, h->sweep_kseg);
