@@ -65,10 +65,8 @@ struct StoreBF16 {
   static constexpr bool dev = true;
   __device__ static C raw(T v) { return __uint_as_float(uint32_t(v) << 16); }
   __device__ static T enc(C x, C winv, C r) { return enc_dev(x * winv - r); }
-  __device__ static T enc_dev(C d) {  // a deviation already in units of w
-    uint32_t u = __float_as_uint(d);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return T(u >> 16);
+  __device__ static T enc_dev(C d) {  // a deviation already in units of w; round to nearest even
+    return __builtin_bit_cast(T, __bf16(d));
   }
 };
 
