@@ -488,3 +488,65 @@ def test_vortex_is_isentropic_with_given_peak_mach():
     u_l = 1.2 * c_l
     swirl = np.hypot(wl.ux - u_l, wl.uy)[:, left]
     assert abs(swirl.max() / (0.25 * c_l) - 1) < 0.01
+
+
+# ---------------------------------------------------------------- derivatives of the step
+@pytest.mark.parametrize("split", SPLITS)
+@pytest.mark.parametrize("Pr", (0.6, 1.7))
+def test_step_derivatives_forward_reverse_and_differences(split, Pr):
+    """The derivatives of one oracle step, which the GPU adjoint tests take as
+    their reference by reverse mode, checked by two other routes.
+    * <J v, w> = <v, J^T w>: forward-mode tangents against reverse mode, for
+      random directions in the populations, tau_ref and Pr.
+    * Central differences of the step in float64 against forward mode along
+      tau_ref, along Pr, and along a population direction that is constant
+      over the grid in each plane: that direction leaves every spatial
+      difference, and so every branch of the limiter, unchanged, so the step
+      is smooth along it.  (A direction that varies in space moves faces
+      across the limiter's kinks, where differences measure secants.)"""
+    import torch.autograd.forward_ad as fwAD
+
+    wl = smooth_random(9, 7, seed=4, amp_T=0.05)
+    cfg = O.Config(nx=9, ny=7, split=split, dx=wl.dx, dy=wl.dy, Pr=Pr, tau_ref=0.02, R=1.1, T_ref=0.9,
+                   gamma=1.3, bc_x=O.PERIODIC, bc_y=O.ZERO_GRADIENT)
+    f0, g0 = O.initial_state(wl.rho, wl.ux, wl.uy, wl.T, cfg)
+    rng = np.random.default_rng(1)
+    X = torch.stack([f0, g0]) * (1 + 0.01 * torch.tensor(rng.standard_normal((2,) + tuple(f0.shape))))
+    dt, tau0 = 3e-3, 0.02
+    t64 = lambda a: torch.tensor(a, dtype=torch.float64)  # noqa: E731
+
+    def jvp(v, vt, vp):
+        with fwAD.dual_level():
+            fd = fwAD.make_dual(X[0].clone(), v[0])
+            gd = fwAD.make_dual(X[1].clone(), v[1])
+            fn, gn = O.step(fd, gd, cfg, dt, fwAD.make_dual(t64(tau0), t64(vt)), fwAD.make_dual(t64(Pr), t64(vp)))
+            return torch.stack([fwAD.unpack_dual(fn).tangent, fwAD.unpack_dual(gn).tangent])
+
+    def central(v, vt, vp, h):
+        def moved(s):
+            Y = X + s * h * v
+            return torch.stack(O.step(Y[0], Y[1], cfg, dt, t64(tau0 + s * h * vt), t64(Pr + s * h * vp)))
+        return (moved(1.0) - moved(-1.0)) / (2 * h)
+
+    def rel(a, b):
+        return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+    # forward mode against reverse mode
+    v = torch.tensor(rng.standard_normal(tuple(X.shape)))
+    w = torch.tensor(rng.standard_normal(tuple(X.shape)))
+    vt, vp = 0.3, -0.2
+    Jv = jvp(v, vt, vp)
+    fr, gr = X[0].clone().requires_grad_(), X[1].clone().requires_grad_()
+    taur, prr = t64(tau0).requires_grad_(), t64(Pr).requires_grad_()
+    fn, gn = O.step(fr, gr, cfg, dt, taur, prr)
+    ((w[0] * fn).sum() + (w[1] * gn).sum()).backward()
+    lhs = float((Jv * w).sum())
+    rhs = float((v[0] * fr.grad).sum() + (v[1] * gr.grad).sum() + vt * taur.grad + vp * prr.grad)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+    # forward mode against central differences
+    zero = torch.zeros_like(X)
+    assert rel(central(zero, 1.0, 0.0, 1e-6), jvp(zero, 1.0, 0.0)) < 1e-7
+    assert rel(central(zero, 0.0, 1.0, 1e-5), jvp(zero, 0.0, 1.0)) < 1e-6
+    u = torch.tensor(rng.standard_normal((2, X.shape[1], 1, 1))).expand_as(X) * X.abs().mean()
+    assert rel(central(u, 0.0, 0.0, 1e-6), jvp(u, 0.0, 0.0)) < 1e-7
