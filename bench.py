@@ -280,13 +280,14 @@ def adjoint_cost(device, n=256, nsteps=200, storage="f32", Ks=(10, 50)):
         s.close()
         return T
 
-    def with_gradient(K, overlap=False):
+    def with_gradient(K, overlap=False, cotangent="f64"):
         T0t = torch.tensor(T0, device=device, requires_grad=True)
         tau = torch.tensor(tau0, dtype=torch.float64, requires_grad=True)
         prt = torch.tensor(Pr, dtype=torch.float64, requires_grad=True)
-        out = rollout_temperature(T0t, tau, prt, ones, zeros, zeros, nsteps, K=K, overlap=overlap, **kw)
+        out = rollout_temperature(T0t, tau, prt, ones, zeros, zeros, nsteps, K=K, overlap=overlap,
+                                  cotangent=cotangent, **kw)
         ((out - tgt) ** 2).sum().backward()
-        return T0t.grad
+        return T0t.grad, tau.grad, prt.grad
 
     def timed(fn, reps=3):
         fn()
@@ -304,7 +305,15 @@ def adjoint_cost(device, n=256, nsteps=200, storage="f32", Ks=(10, 50)):
         t = timed(lambda: with_gradient(K))
         res[f"K{K}_s"] = t
         res[f"K{K}_ratio"] = t / t_fwd
-    # the same with the recomputation on a second stream
+        # float32 cotangents: time, and the gradient (T0, tau_ref, Pr) against the float64 one
+        t = timed(lambda: with_gradient(K, cotangent="f32"))
+        res[f"K{K}_f32_cotangent_ratio"] = t / t_fwd
+    g64, g32 = with_gradient(Ks[0]), with_gradient(Ks[0], cotangent="f32")
+    res["f32_cotangent_rel_err"] = {
+        "T0": float(torch.linalg.vector_norm(g32[0] - g64[0]) / torch.linalg.vector_norm(g64[0])),
+        "tau_ref": float(abs(g32[1] - g64[1]) / abs(g64[1])),
+        "Pr": float(abs(g32[2] - g64[2]) / abs(g64[2]))}
+    # the recomputation on a second stream
     t = timed(lambda: with_gradient(Ks[0], overlap=True))
     res[f"K{Ks[0]}_overlap_ratio"] = t / t_fwd
     return res

@@ -201,6 +201,16 @@ size_t dvbm_adjoint_work_bytes(const dvbm_params* p);
 int dvbm_adjoint_step(dvbm_handle* h, const void* state_n, const double* lam_np1, double* lam_n,
                       double* dparams, void* work);
 
+/* dvbm_adjoint_step with the cotangents stored in float32: lam_np1 and lam_n
+ * are dense device float arrays lam[2][Q][ny][nx] (half of
+ * dvbm_adjoint_bytes()).  Values are widened to float64 on load, all
+ * arithmetic, the work array and dparams are float64, and lam_n is rounded to
+ * nearest once on store, so a step adds one float32 rounding (2^-24 relative)
+ * per value; it halves the cotangent traffic of a reverse sweep.  Arguments,
+ * errors and ordering as for dvbm_adjoint_step.  Asynchronous. */
+int dvbm_adjoint_step_f32(dvbm_handle* h, const void* state_n, const float* lam_np1, float* lam_n,
+                          double* dparams, void* work);
+
 /* lam = sum of (d field / dX)^T d_field over the macroscopic fields of state
  * (rho, u_x, u_y, T of Eqs. eq_quadratur1-3); any d_* may be NULL (zero).
  * d_* are device float64 arrays of ny*nx.  Asynchronous. */

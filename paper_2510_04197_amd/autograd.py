@@ -20,7 +20,7 @@ from .dvbm import Solver, make_params
 
 class _Rollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, T0, tau_ref, Pr, rho0, ux0, uy0, nsteps, K, overlap, params_kw):
+    def forward(ctx, T0, tau_ref, Pr, rho0, ux0, uy0, nsteps, K, overlap, cotangent, params_kw):
         if not params_kw.get("dt", 0.0) > 0.0:
             raise ValueError("rollout_temperature needs an explicit dt > 0")
         ny, nx = T0.shape
@@ -38,6 +38,7 @@ class _Rollout(torch.autograd.Function):
         ctx.ckpts = ckpts
         ctx.final = s.state_buffer.clone()
         ctx.nsteps, ctx.K, ctx.overlap = nsteps, K, overlap
+        ctx.lam_dtype = {"f64": torch.float64, "f32": torch.float32}[cotangent]
         ctx.fields0 = (rho0, ux0, uy0, T0.detach())
         ctx.pdev = (tau_ref.device if torch.is_tensor(tau_ref) else None,
                     Pr.device if torch.is_tensor(Pr) else None)
@@ -47,7 +48,7 @@ class _Rollout(torch.autograd.Function):
     def backward(ctx, gT):
         s: Solver = ctx.solver
         dev = gT.device
-        lam = s.adjoint_moments(ctx.final, d_T=gT.contiguous())
+        lam = s.adjoint_moments(ctx.final, d_T=gT.contiguous()).to(ctx.lam_dtype)
         lam_tmp = torch.empty_like(lam)
         dparams = torch.zeros(2, dtype=torch.float64, device=dev)
         nsteps, K = ctx.nsteps, ctx.K
@@ -63,6 +64,9 @@ class _Rollout(torch.autograd.Function):
             side.wait_stream(main)  # the checkpoints and the forward state are ready
             r = Solver(s.params, *ctx.fields0, device=dev, stream=side)
             bufs = [torch.empty((max(K - 1, 1), nb), dtype=torch.uint8, device=dev) for _ in range(2)]
+            # memory the side stream uses is not handed out again before its work is done
+            for tns in bufs + ctx.ckpts + r.buffers + [r.workspace] + list(r._fields0):
+                tns.record_stream(side)
         else:
             side, r = main, s
             bufs = [torch.empty((max(K - 1, 1), nb), dtype=torch.uint8, device=dev)] * 2
@@ -102,15 +106,16 @@ class _Rollout(torch.autograd.Function):
         if ctx.overlap:
             main.wait_stream(side)
             r.close()
-        g = s.adjoint_init(lam, *ctx.fields0, which=("T",))["T"]
+        g = s.adjoint_init(lam.to(torch.float64), *ctx.fields0, which=("T",))["T"]
         s.close()
         dtau = dparams[0].to(ctx.pdev[0]) if ctx.pdev[0] is not None else None
         dpr = dparams[1].to(ctx.pdev[1]) if ctx.pdev[1] is not None else None
-        return g, dtau, dpr, None, None, None, None, None, None, None
+        return g, dtau, dpr, None, None, None, None, None, None, None, None
 
 
 def rollout_temperature(T0: torch.Tensor, tau_ref: torch.Tensor, Pr: torch.Tensor, rho0, ux0, uy0,
-                        nsteps: int, K: int = 10, overlap: bool = False, **params_kw) -> torch.Tensor:
+                        nsteps: int, K: int = 10, overlap: bool = False, cotangent: str = "f64",
+                        **params_kw) -> torch.Tensor:
     """Final temperature after ``nsteps`` steps; differentiable in ``T0``, ``tau_ref`` and ``Pr``.
 
     ``T0`` is a float64 CUDA tensor of shape ``(ny, nx)``; ``tau_ref`` and
@@ -120,6 +125,11 @@ def rollout_temperature(T0: torch.Tensor, tau_ref: torch.Tensor, Pr: torch.Tenso
     the next segment on a second stream during each reverse sweep, at the cost
     of a second buffer of ``K - 1`` states (on a 256 x 256 grid the two streams
     slow each other down: the reverse sweep's kernels already keep the memory
-    system busy).
+    system busy).  ``cotangent="f32"`` stores the cotangents of the reverse
+    sweep in float32 (``dvbm_adjoint_step_f32``; the arithmetic stays float64),
+    which halves their memory traffic at one float32 rounding per value and step.
     """
-    return _Rollout.apply(T0, tau_ref, Pr, rho0, ux0, uy0, int(nsteps), int(K), bool(overlap), dict(params_kw))
+    if cotangent not in ("f64", "f32"):
+        raise ValueError("cotangent must be 'f64' or 'f32'")
+    return _Rollout.apply(T0, tau_ref, Pr, rho0, ux0, uy0, int(nsteps), int(K), bool(overlap), cotangent,
+                          dict(params_kw))

@@ -355,8 +355,8 @@ __device__ inline double adj_X(const typename S::T* __restrict__ state, const KP
   return weight<SPLIT>(i) * (r + double(S::raw(v)));
 }
 
-template <int SPLIT, class S, int PRM>
-__device__ inline void cell_adjoint_relax(const typename S::T* __restrict__ state, const double* __restrict__ lam1,
+template <int SPLIT, class S, int PRM, class LT>
+__device__ inline void cell_adjoint_relax(const typename S::T* __restrict__ state, const LT* __restrict__ lam1,
                                           double* __restrict__ work, const KParams& kp, int c, double tau_ref,
                                           double& g_tau, double& g_pr) {
   constexpr int N1 = Set<SPLIT>::N1;
@@ -388,7 +388,7 @@ __device__ inline void cell_adjoint_relax(const typename S::T* __restrict__ stat
 #pragma unroll
     for (int b = 0; b < N1; ++b) {
       const int i = a * N1 + b;
-      const double lf = lam1[int64_t(i) * cells + c], lg = lam1[int64_t(Q + i) * cells + c];
+      const double lf = double(lam1[int64_t(i) * cells + c]), lg = double(lam1[int64_t(Q + i) * cells + c]);
       const double xb = L::xi(b), wb = L::w(b);
 #pragma unroll
       for (int q = 0; q <= NF; ++q) {
@@ -473,9 +473,9 @@ constexpr int ADJ_STRIP = 58;
 // The relaxation part comes from the work array, read once per row for all
 // N1 planes: with xi_a fixed the Hermite polynomial of the moment cotangents
 // is a cubic (f) or linear (g) polynomial in xi_b.
-template <int SPLIT, class S, int BCX, int BCY, int D>
-__device__ inline void sweep_adjoint_flux(const typename S::T* __restrict__ state, const double* __restrict__ lam1,
-                                          const double* __restrict__ work, double* __restrict__ lam0,
+template <int SPLIT, class S, int BCX, int BCY, int D, class LT>
+__device__ inline void sweep_adjoint_flux(const typename S::T* __restrict__ state, const LT* __restrict__ lam1,
+                                          const double* __restrict__ work, LT* __restrict__ lam0,
                                           const KParams& kp, int a, int x0, int ya, int yb) {
   constexpr int N1 = Set<SPLIT>::N1;
   constexpr int Q = Set<SPLIT>::Q;
@@ -490,7 +490,7 @@ __device__ inline void sweep_adjoint_flux(const typename S::T* __restrict__ stat
   const double beta = 0.5 * kp.beta2;
   const double kvx = kp.kx * xa;
   const int pl0 = D * Q + a * N1;
-  const double* lp = lam1 + int64_t(pl0) * cells + gx;
+  const LT* lp = lam1 + int64_t(pl0) * cells + gx;
 
   constexpr int NW = D == 0 ? 11 : 4;  // work rows read: 0..9 and 13 (f), 10..13 (g)
   double X[N1][4], Lm[N1][4], p1[N1], p2[N1], gs[N1];
@@ -505,7 +505,7 @@ __device__ inline void sweep_adjoint_flux(const typename S::T* __restrict__ stat
 #pragma unroll
     for (int b = 0; b < N1; ++b) {
       X[b][s] = adj_X<SPLIT, S>(state, kp, D, a * N1 + b, ry, gx);
-      Lm[b][s] = lp[int64_t(b) * cells + int64_t(ry) * kp.nx];
+      Lm[b][s] = double(lp[int64_t(b) * cells + int64_t(ry) * kp.nx]);
     }
   };
 
@@ -596,7 +596,7 @@ __device__ inline void sweep_adjoint_flux(const typename S::T* __restrict__ stat
       } else {
         out += w[0] + w[1] * xa + w[2] * xb + w[3] * Lm[b][s0];
       }
-      if (own) lam0[int64_t(pl0 + b) * cells + int64_t(c) * kp.nx + x] = out;
+      if (own) lam0[int64_t(pl0 + b) * cells + int64_t(c) * kp.nx + x] = LT(out);
     }
   };
 

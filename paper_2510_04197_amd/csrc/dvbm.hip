@@ -353,16 +353,16 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(const double* __restrict
 // dparams != NULL the (d/dtau_ref, d/dPr) block partials go to
 // partials[4 * blockIdx.x], and the last block to finish (counted in
 // *ticket, which it resets) adds their sum, in block order, to dparams.
-template <int SPLIT, class S, int PRM>
+template <int SPLIT, class S, int PRM, class LT>
 __global__ __launch_bounds__(RED_THREADS) void k_adjoint_relax(const typename S::T* __restrict__ state,
-                                                               const double* __restrict__ lam1,
+                                                               const LT* __restrict__ lam1,
                                                                double* __restrict__ work, KParams kp,
                                                                double tau_ref, double* partials,
                                                                unsigned* ticket, double* dparams) {
   const int cells = kp.nx * kp.ny;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += gridDim.x * blockDim.x)
-    cell_adjoint_relax<SPLIT, S, PRM>(state, lam1, work, kp, c, tau_ref, acc[0], acc[1]);
+    cell_adjoint_relax<SPLIT, S, PRM, LT>(state, lam1, work, kp, c, tau_ref, acc[0], acc[1]);
   if (!dparams) return;
   const int mode[4] = {0, 0, 0, 0};
   block_reduce4(acc, mode, partials + 4 * blockIdx.x);
@@ -399,10 +399,10 @@ __global__ __launch_bounds__(RED_THREADS) void k_adjoint_relax(const typename S:
 #ifndef DVBM_ADJ_CH_MIN
 #define DVBM_ADJ_CH_MIN 8  // fewest rows per wave (each range walks two rows more)
 #endif
-template <int SPLIT, class S, int BCX, int BCY>
+template <int SPLIT, class S, int BCX, int BCY, class LT>
 __global__ __launch_bounds__(256) void k_adjoint_flux(const typename S::T* __restrict__ state,
-                                                      const double* __restrict__ lam1,
-                                                      const double* __restrict__ work, double* __restrict__ lam0,
+                                                      const LT* __restrict__ lam1,
+                                                      const double* __restrict__ work, LT* __restrict__ lam0,
                                                       KParams kp, int nstrips, int ch, int nchunks) {
   constexpr int N1 = Set<SPLIT>::N1;
   const int nb = int(gridDim.x), blk = int(blockIdx.x);
@@ -414,9 +414,9 @@ __global__ __launch_bounds__(256) void k_adjoint_flux(const typename S::T* __res
   if (chunk >= nchunks) return;
   const int ya = chunk * ch, yb = ya + ch < kp.ny ? ya + ch : kp.ny;
   if (g < N1)
-    sweep_adjoint_flux<SPLIT, S, BCX, BCY, 0>(state, lam1, work, lam0, kp, g, strip * ADJ_STRIP, ya, yb);
+    sweep_adjoint_flux<SPLIT, S, BCX, BCY, 0, LT>(state, lam1, work, lam0, kp, g, strip * ADJ_STRIP, ya, yb);
   else
-    sweep_adjoint_flux<SPLIT, S, BCX, BCY, 1>(state, lam1, work, lam0, kp, g - N1, strip * ADJ_STRIP, ya, yb);
+    sweep_adjoint_flux<SPLIT, S, BCX, BCY, 1, LT>(state, lam1, work, lam0, kp, g - N1, strip * ADJ_STRIP, ya, yb);
 }
 
 template <int SPLIT, class S>
@@ -666,27 +666,26 @@ void step(const dvbm_handle* h, const void* src, void* dst) {
     launch_step_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_ZERO_GRADIENT>(h, src, dst);
 }
 
-template <int SPLIT, class S, int BCX, int BCY>
-void adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, double* lam0, double* dparams,
-                double* work);
+template <int SPLIT, class S, int BCX, int BCY, class LT>
+void adjoint_bc(const dvbm_handle* h, const void* state, const LT* lam1, LT* lam0, double* dparams, double* work);
 
-template <int SPLIT, class S>
-void adjoint(const dvbm_handle* h, const void* state, const double* lam1, double* lam0, double* dparams,
-             double* work) {
+// Cotangents lam1, lam0 stored as LT (double or float); the arithmetic and the
+// work array are float64.
+template <int SPLIT, class S, class LT>
+void adjoint(const dvbm_handle* h, const void* state, const LT* lam1, LT* lam0, double* dparams, double* work) {
   const int bx = h->p.bc_x, by = h->p.bc_y;
   if (bx == DVBM_PERIODIC && by == DVBM_PERIODIC)
-    adjoint_bc<SPLIT, S, BC_PERIODIC, BC_PERIODIC>(h, state, lam1, lam0, dparams, work);
+    adjoint_bc<SPLIT, S, BC_PERIODIC, BC_PERIODIC, LT>(h, state, lam1, lam0, dparams, work);
   else if (bx == DVBM_ZERO_GRADIENT && by == DVBM_PERIODIC)
-    adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_PERIODIC>(h, state, lam1, lam0, dparams, work);
+    adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_PERIODIC, LT>(h, state, lam1, lam0, dparams, work);
   else if (bx == DVBM_PERIODIC && by == DVBM_ZERO_GRADIENT)
-    adjoint_bc<SPLIT, S, BC_PERIODIC, BC_ZERO_GRADIENT>(h, state, lam1, lam0, dparams, work);
+    adjoint_bc<SPLIT, S, BC_PERIODIC, BC_ZERO_GRADIENT, LT>(h, state, lam1, lam0, dparams, work);
   else
-    adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_ZERO_GRADIENT>(h, state, lam1, lam0, dparams, work);
+    adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_ZERO_GRADIENT, LT>(h, state, lam1, lam0, dparams, work);
 }
 
-template <int SPLIT, class S, int BCX, int BCY>
-void adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, double* lam0, double* dparams,
-                double* work) {
+template <int SPLIT, class S, int BCX, int BCY, class LT>
+void adjoint_bc(const dvbm_handle* h, const void* state, const LT* lam1, LT* lam0, double* dparams, double* work) {
   using T = typename S::T;
   const T* s = static_cast<const T*>(state);
   const double tau = h->p.tau_ref;
@@ -696,15 +695,15 @@ void adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, dou
   const dim3 grid(unsigned(nb < ADJ_RELAX_BLOCKS ? nb : ADJ_RELAX_BLOCKS)), block(RED_THREADS);
   switch (pr_mode(h->p.Pr)) {
     case PR_UNIT:
-      hipLaunchKernelGGL((k_adjoint_relax<SPLIT, S, PR_UNIT>), grid, block, 0, h->stream, s, lam1, work, h->kp, tau,
+      hipLaunchKernelGGL((k_adjoint_relax<SPLIT, S, PR_UNIT, LT>), grid, block, 0, h->stream, s, lam1, work, h->kp, tau,
                          h->ws, ticket, dparams);
       break;
     case PR_LOW:
-      hipLaunchKernelGGL((k_adjoint_relax<SPLIT, S, PR_LOW>), grid, block, 0, h->stream, s, lam1, work, h->kp, tau,
+      hipLaunchKernelGGL((k_adjoint_relax<SPLIT, S, PR_LOW, LT>), grid, block, 0, h->stream, s, lam1, work, h->kp, tau,
                          h->ws, ticket, dparams);
       break;
     default:
-      hipLaunchKernelGGL((k_adjoint_relax<SPLIT, S, PR_HIGH>), grid, block, 0, h->stream, s, lam1, work, h->kp, tau,
+      hipLaunchKernelGGL((k_adjoint_relax<SPLIT, S, PR_HIGH, LT>), grid, block, 0, h->stream, s, lam1, work, h->kp, tau,
                          h->ws, ticket, dparams);
       break;
   }
@@ -712,7 +711,7 @@ void adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, dou
   int64_t ch = (int64_t(h->p.ny) * groups * nstrips + DVBM_ADJ_WAVES - 1) / DVBM_ADJ_WAVES;
   ch = ch < DVBM_ADJ_CH_MIN ? DVBM_ADJ_CH_MIN : (ch > h->p.ny ? h->p.ny : ch);
   const int64_t nchunks = (h->p.ny + ch - 1) / ch, waves = groups * nstrips * nchunks;
-  hipLaunchKernelGGL((k_adjoint_flux<SPLIT, S, BCX, BCY>), dim3(unsigned((waves + 3) / 4)), dim3(256), 0, h->stream,
+  hipLaunchKernelGGL((k_adjoint_flux<SPLIT, S, BCX, BCY, LT>), dim3(unsigned((waves + 3) / 4)), dim3(256), 0, h->stream,
                      s, lam1, work, lam0, h->kp, int(nstrips), int(ch), int(nchunks));
 }
 
@@ -722,16 +721,19 @@ void adjoint_bc(const dvbm_handle* h, const void* state, const double* lam1, dou
 // kernel unit DVBM_PART = 4 (split - 1) + storage + 1
 template void dvbm_launch::step<(DVBM_PART - 1) / 4 + 1, DVBM_PART_STORE>(const dvbm_handle*, const void*, void*);
 #if (DVBM_PART - 1) % 4 < 2
-template void dvbm_launch::adjoint<(DVBM_PART - 1) / 4 + 1, DVBM_PART_STORE>(const dvbm_handle*, const void*,
-                                                                            const double*, double*, double*,
-                                                                            double*);
+template void dvbm_launch::adjoint<(DVBM_PART - 1) / 4 + 1, DVBM_PART_STORE, double>(
+    const dvbm_handle*, const void*, const double*, double*, double*, double*);
+template void dvbm_launch::adjoint<(DVBM_PART - 1) / 4 + 1, DVBM_PART_STORE, float>(
+    const dvbm_handle*, const void*, const float*, float*, double*, double*);
 #endif
 #else
 #define DVBM_EXTERN_STEP(SPLIT, S) \
   extern template void dvbm_launch::step<SPLIT, S>(const dvbm_handle*, const void*, void*);
-#define DVBM_EXTERN_ADJ(SPLIT, S)                                                                          \
-  extern template void dvbm_launch::adjoint<SPLIT, S>(const dvbm_handle*, const void*, const double*, \
-                                                      double*, double*, double*);
+#define DVBM_EXTERN_ADJ(SPLIT, S)                                                                           \
+  extern template void dvbm_launch::adjoint<SPLIT, S, double>(const dvbm_handle*, const void*, const double*, \
+                                                              double*, double*, double*);                   \
+  extern template void dvbm_launch::adjoint<SPLIT, S, float>(const dvbm_handle*, const void*, const float*,   \
+                                                             float*, double*, double*);
 DVBM_EXTERN_STEP(1, StoreF64)
 DVBM_EXTERN_STEP(1, StoreF32)
 DVBM_EXTERN_STEP(1, StoreBF16)
@@ -812,9 +814,10 @@ struct EncodeOp {
 
 template <int SPLIT, class S>
 struct AdjointOp {
-  static void run(const dvbm_handle* h, const void* state, const double* lam1, double* lam0, double* dparams,
+  template <class LT>
+  static void run(const dvbm_handle* h, const void* state, const LT* lam1, LT* lam0, double* dparams,
                   double* work) {
-    dvbm_launch::adjoint<SPLIT, S>(h, state, lam1, lam0, dparams, work);
+    dvbm_launch::adjoint<SPLIT, S, LT>(h, state, lam1, lam0, dparams, work);
   }
 };
 
@@ -1055,6 +1058,17 @@ int dvbm_adjoint_step(dvbm_handle* h, const void* state_n, const double* lam_np1
   if (!h || !state_n || !lam_np1 || !lam_n || !work) return fail(DVBM_EINVAL, "dvbm_adjoint_step: NULL argument");
   if (lam_np1 == lam_n) return fail(DVBM_EINVAL, "dvbm_adjoint_step: lam_np1 and lam_n must differ");
   if (int rc = adjoint_storage_ok(h, "dvbm_adjoint_step")) return rc;
+  dispatch_adjoint<AdjointOp>(h->p, h, state_n, lam_np1, lam_n, dparams, static_cast<double*>(work));
+  HIP_TRY(hipGetLastError());
+  return DVBM_OK;
+}
+
+int dvbm_adjoint_step_f32(dvbm_handle* h, const void* state_n, const float* lam_np1, float* lam_n,
+                          double* dparams, void* work) {
+  if (!h || !state_n || !lam_np1 || !lam_n || !work)
+    return fail(DVBM_EINVAL, "dvbm_adjoint_step_f32: NULL argument");
+  if (lam_np1 == lam_n) return fail(DVBM_EINVAL, "dvbm_adjoint_step_f32: lam_np1 and lam_n must differ");
+  if (int rc = adjoint_storage_ok(h, "dvbm_adjoint_step_f32")) return rc;
   dispatch_adjoint<AdjointOp>(h->p, h, state_n, lam_np1, lam_n, dparams, static_cast<double*>(work));
   HIP_TRY(hipGetLastError());
   return DVBM_OK;

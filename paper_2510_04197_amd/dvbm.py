@@ -67,6 +67,7 @@ SIGNATURES = {
     "dvbm_adjoint_bytes": (ctypes.c_size_t, [_PP]),
     "dvbm_adjoint_work_bytes": (ctypes.c_size_t, [_PP]),
     "dvbm_adjoint_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "dvbm_adjoint_step_f32": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "dvbm_adjoint_moments": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "dvbm_adjoint_init": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "dvbm_last_error": (ctypes.c_char_p, []),
@@ -223,18 +224,24 @@ class Solver:
         return X
 
     # ------------------------------------------------------------------ adjoint
-    def new_cotangent(self) -> torch.Tensor:
-        """A zeroed dense float64 cotangent ``[2, Q, ny, nx]``."""
-        return torch.zeros((2, self.Q, self.params.ny, self.params.nx), dtype=torch.float64, device=self.device)
+    def new_cotangent(self, dtype: torch.dtype = torch.float64) -> torch.Tensor:
+        """A zeroed dense cotangent ``[2, Q, ny, nx]`` (float64, or float32 for :meth:`adjoint_step`)."""
+        return torch.zeros((2, self.Q, self.params.ny, self.params.nx), dtype=dtype, device=self.device)
 
     def adjoint_step(self, state: torch.Tensor, lam_next: torch.Tensor, lam: torch.Tensor,
                      dparams: torch.Tensor | None = None):
-        """``lam = (dX'/dX)^T lam_next`` at ``state``; ``dparams`` (float64[2]) += (d/dtau_ref, d/dPr)."""
+        """``lam = (dX'/dX)^T lam_next`` at ``state``; ``dparams`` (float64[2]) += (d/dtau_ref, d/dPr).
+
+        ``lam_next`` and ``lam`` are both float64 (``dvbm_adjoint_step``) or both
+        float32 (``dvbm_adjoint_step_f32``: float32 storage, float64 arithmetic)."""
+        if lam_next.dtype != lam.dtype or lam.dtype not in (torch.float64, torch.float32):
+            raise TypeError("lam_next and lam must both be float64 or both float32")
         if getattr(self, "_adj_work", None) is None:
             nbytes = self.lib.dvbm_adjoint_work_bytes(ctypes.byref(self.params))
             self._adj_work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        _check(self.lib.dvbm_adjoint_step(self.handle, _ptr(state), _ptr(lam_next), _ptr(lam),
-                                          _ptr(dparams) if dparams is not None else None, _ptr(self._adj_work)))
+        fn = self.lib.dvbm_adjoint_step if lam.dtype == torch.float64 else self.lib.dvbm_adjoint_step_f32
+        _check(fn(self.handle, _ptr(state), _ptr(lam_next), _ptr(lam), _ptr(dparams) if dparams is not None else None,
+                  _ptr(self._adj_work)))
 
     def adjoint_moments(self, state: torch.Tensor, d_rho=None, d_ux=None, d_uy=None, d_T=None) -> torch.Tensor:
         """Cotangent of the populations of ``state`` from cotangents of its fields."""

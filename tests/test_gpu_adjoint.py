@@ -96,6 +96,33 @@ def test_step_adjoint_grid_shapes(shape, bc):
     check_step_adjoint(step_adjoint_vs_oracle(shape[0], shape[1], 2, 0.71, bc[0], bc[1], "f64", seed=3))
 
 
+@pytest.mark.parametrize("storage", ("f64", "f32"))
+@pytest.mark.parametrize("bc", (BCS[0], BCS[3]), ids=lambda b: f"{b[0][0]}{b[1][0]}")
+def test_step_adjoint_float32_cotangents(storage, bc):
+    """dvbm_adjoint_step_f32 equals dvbm_adjoint_step on the same (float32)
+    lam': the arithmetic is float64 in both, so lam differs by its final
+    rounding to float32 only, and d/dtau_ref, d/dPr by summation order at most."""
+    wl = smooth_random(117, 17, seed=5)
+    p = make_params(wl.nx, wl.ny, dx=wl.dx, dy=wl.dy, split=2, storage=storage, Pr=0.7, tau_ref=0.02,
+                    bc_x=bc[0], bc_y=bc[1], dt=3e-3)
+    s = Solver(p, wl.rho, wl.ux, wl.uy, wl.T, device=DEV)
+    rng = np.random.default_rng(2)
+    lam1 = torch.tensor(rng.standard_normal((2, 25, wl.ny, wl.nx)), device=DEV).float()
+    out = {}
+    for dt_ in (torch.float64, torch.float32):
+        lam0 = s.new_cotangent(dt_)
+        dpar = torch.zeros(2, dtype=torch.float64, device=DEV)
+        s.adjoint_step(s.state_buffer, lam1.to(dt_), lam0, dpar)
+        torch.cuda.synchronize()
+        out[dt_] = (lam0.cpu(), dpar.cpu())
+    s.close()
+    l64, d64 = out[torch.float64]
+    l32, d32 = out[torch.float32]
+    assert l32.dtype == torch.float32
+    assert torch.equal(l32, l64.float())  # one rounding of the same float64 value
+    assert torch.allclose(d32, d64, rtol=1e-14, atol=0.0)
+
+
 @pytest.mark.parametrize("split", (1, 2))
 def test_readout_and_initial_adjoints(split):
     wl = smooth_random(66, 9, seed=12)
@@ -164,6 +191,24 @@ def test_rollout_gradient_matches_oracle():
     assert rel(T0t.grad.cpu(), T0o.grad) < 1e-10
     assert abs(float(tau.grad) / float(tauo.grad) - 1) < 1e-10
     assert abs(float(prt.grad) / float(pro.grad) - 1) < 1e-10
+
+
+def test_rollout_float32_cotangents():
+    """Gradients with float32 cotangents (12 steps, K = 5) against float64
+    cotangents: within 1e-5 relative for T0, tau_ref and Pr."""
+    bump, T0, zeros, kw, nsteps, Pr = _loss_problem()
+    n = T0.shape[0]
+    grads = {}
+    for cot in ("f64", "f32"):
+        T0t = torch.tensor(T0, device=DEV, requires_grad=True)
+        tau = torch.tensor(0.01, dtype=torch.float64, requires_grad=True)
+        prt = torch.tensor(Pr, dtype=torch.float64, requires_grad=True)
+        out = rollout_temperature(T0t, tau, prt, np.ones((n, n)), zeros, zeros, nsteps, K=5, cotangent=cot, **kw)
+        ((out - torch.tensor(bump.T, device=DEV)) ** 2).sum().backward()
+        grads[cot] = (T0t.grad.cpu(), float(tau.grad), float(prt.grad))
+    assert rel(grads["f32"][0], grads["f64"][0]) < 1e-5
+    assert abs(grads["f32"][1] / grads["f64"][1] - 1) < 1e-5
+    assert abs(grads["f32"][2] / grads["f64"][2] - 1) < 1e-5
 
 
 @pytest.mark.parametrize("K", (1, 5, 12, 20))
