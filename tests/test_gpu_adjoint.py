@@ -96,18 +96,19 @@ def test_step_adjoint_grid_shapes(shape, bc):
     check_step_adjoint(step_adjoint_vs_oracle(shape[0], shape[1], 2, 0.71, bc[0], bc[1], "f64", seed=3))
 
 
+@pytest.mark.parametrize("split", (1, 2))
 @pytest.mark.parametrize("storage", ("f64", "f32"))
 @pytest.mark.parametrize("bc", (BCS[0], BCS[3]), ids=lambda b: f"{b[0][0]}{b[1][0]}")
-def test_step_adjoint_float32_cotangents(storage, bc):
+def test_step_adjoint_float32_cotangents(split, storage, bc):
     """dvbm_adjoint_step_f32 equals dvbm_adjoint_step on the same (float32)
     lam': the arithmetic is float64 in both, so lam differs by its final
     rounding to float32 only, and d/dtau_ref, d/dPr by summation order at most."""
     wl = smooth_random(117, 17, seed=5)
-    p = make_params(wl.nx, wl.ny, dx=wl.dx, dy=wl.dy, split=2, storage=storage, Pr=0.7, tau_ref=0.02,
+    p = make_params(wl.nx, wl.ny, dx=wl.dx, dy=wl.dy, split=split, storage=storage, Pr=0.7, tau_ref=0.02,
                     bc_x=bc[0], bc_y=bc[1], dt=3e-3)
     s = Solver(p, wl.rho, wl.ux, wl.uy, wl.T, device=DEV)
     rng = np.random.default_rng(2)
-    lam1 = torch.tensor(rng.standard_normal((2, 25, wl.ny, wl.nx)), device=DEV).float()
+    lam1 = torch.tensor(rng.standard_normal((2, s.Q, wl.ny, wl.nx)), device=DEV).float()
     out = {}
     for dt_ in (torch.float64, torch.float32):
         lam0 = s.new_cotangent(dt_)
