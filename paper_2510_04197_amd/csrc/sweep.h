@@ -122,6 +122,69 @@ __device__ inline void half_moments(const R* v, double* out) {
   for (int k = 0; k < NM; ++k) out[k] = acc[k];
 }
 
+// The same moments of w_i v_i, for values v in units of the weight (the
+// deviations the 16-bit formats store): the weights enter the float64
+// coefficients of the sums, so no value is scaled first.
+template <int D, int N1, class R>
+__device__ inline void half_moments_w(const R* v, double* out) {
+  using L = GH<N1>;
+  constexpr int NM = D == 0 ? 10 : 3;
+  double acc[NM];
+#pragma unroll
+  for (int k = 0; k < NM; ++k) acc[k] = 0.0;
+  // sums over b of w_b v_(a, b) xi_b^k, k = 0..3, folding +-xi_b pairs
+  auto psum = [&](int a, double& s0, double& s1, double& s2, double& s3) {
+    const R* r = v + a * N1;
+    s0 = L::has_zero ? L::w(N1 / 2) * double(r[N1 / 2]) : 0.0;
+    s1 = s2 = s3 = 0.0;
+#pragma unroll
+    for (int k = 0; k < N1 / 2; ++k) {
+      const int pk = N1 - 1 - k;
+      const double x = L::xi(pk), w = L::w(pk);
+      const double e = double(r[pk]) + double(r[k]), o = double(r[pk]) - double(r[k]);
+      s0 += w * e;
+      s1 += (w * x) * o;
+      s2 += (w * x * x) * e;
+      s3 += (w * x * x * x) * o;
+    }
+  };
+  if (L::has_zero) {
+    const double wz = L::w(N1 / 2);
+    double s0, s1, s2, s3;
+    psum(N1 / 2, s0, s1, s2, s3);
+    acc[0] += wz * s0;
+    acc[2] += wz * s1;
+    if (D == 0) {
+      acc[5] += wz * s2;
+      acc[9] += wz * s3;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < N1 / 2; ++k) {
+    const int pa = N1 - 1 - k;
+    const double x = L::xi(pa), w = L::w(pa);
+    double a0, a1, a2, a3, b0, b1, b2, b3;
+    psum(pa, a0, a1, a2, a3);
+    psum(k, b0, b1, b2, b3);
+    const double e0 = a0 + b0, o0 = a0 - b0, e1 = a1 + b1;
+    acc[0] += w * e0;
+    acc[1] += (w * x) * o0;
+    acc[2] += w * e1;
+    if (D == 0) {
+      const double o1 = a1 - b1, e2 = a2 + b2, o2 = a2 - b2;
+      acc[3] += (w * x * x) * e0;
+      acc[4] += (w * x) * o1;
+      acc[5] += w * e2;
+      acc[6] += (w * x * x * x) * o0;
+      acc[7] += (w * x * x) * e1;
+      acc[8] += (w * x) * o2;
+      acc[9] += w * (a3 + b3);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NM; ++k) out[k] = acc[k];
+}
+
 // Moment exchange between the two waves of a strip: 13 float64 moments per
 // lane, double-buffered by row parity so one barrier per row suffices.
 struct SweepShared {
@@ -189,6 +252,18 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
   // face value between c and n, upwind cell c, far-side cell u: c + L(c - u, n - c) / 4
   auto face = [&](R u, R c, R n) -> R { return c + R(0.25) * lim4(c - u, n - c, beta2); };
   auto rest = [&](int i) -> R { return R(D == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i)); };
+  // 16-bit formats: X_i = w_i (r_i + d_i), so a moment is that of w_i r_i
+  // (formed here once, in float64) plus that of w_i d_i (formed per row)
+  constexpr int NM = D == 0 ? 10 : 3;
+  double mref[NM];
+  if constexpr (S::dev) {
+    double vr[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) vr[i] = D == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i);
+    half_moments_w<D, N1>(vr, mref);
+  }
+  // the rest value r_i is the same for every population of f, and of g in split II
+  constexpr bool rest_uniform = D == 0 || SPLIT == 2;
 
   // win[i][(P + r) % 3] holds window row r at phase P = (y - ya) % 3; a
   // row enters the window as its bit pattern and is decoded in place at its
@@ -253,11 +328,14 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
     });
     NodeMoments m;
     {
-      R v[Q];
+      double part[NM];
+      if constexpr (S::dev) {
+        half_moments_w<D, N1>(cen, part);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) v[i] = S::dev ? R(weight<SPLIT>(i)) * (rest(i) + cen[i]) : cen[i];
-      double part[D == 0 ? 10 : 3];
-      half_moments<D, N1>(v, part);
+        for (int k = 0; k < NM; ++k) part[k] += mref[k];
+      } else {
+        half_moments<D, N1>(cen, part);
+      }
       double(*xm)[64] = sh.m[y & 1];
 #pragma unroll
       for (int k = 0; k < (D == 0 ? 10 : 3); ++k) xm[(D == 0 ? 0 : 10) + k][lane] = part[k];
@@ -286,6 +364,7 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
           if (h != 0.0) c[p] += (D == 0 ? bf[p][q] : bg[p][q]) * R(h);
         }
       }
+      if (S::dev && rest_uniform) c[0] -= om1 * rest(0);  // He_0 = 1: the -om1 r term of every population
       static_for<N1>([&](auto ac) {
         constexpr int xa = decltype(ac)::value;
         constexpr int i = xa * N1 + ybn;
@@ -297,7 +376,7 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
         // deviation units d = X/w - r:  d' = (1 - om1) d - om1 r + sum_p He_p(xi_a)/p! c_p
         R xn;
         if (S::dev) {
-          xn = keep * c0 - om1 * rest(i);
+          xn = rest_uniform ? keep * c0 : keep * c0 - om1 * rest(i);
 #pragma unroll
           for (int p = 0; p <= 4; ++p) {
             if (p > N) continue;
