@@ -379,7 +379,7 @@ def main():
         return
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs (domain decomposition with "
+        print(json.dumps({"error": "the library runs on one GPU only; multi-GPU runs (domain decomposition with "
                                    "halo exchange) are not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
