@@ -101,3 +101,31 @@ def test_sweep_kernel_distribution_limit():
     assert lib.dvbm_buffer_bytes(ctypes.byref(p)) > 0
     p = dvbm.make_params(5120, 4224, storage="f32", kernel="cell")
     assert lib.dvbm_buffer_bytes(ctypes.byref(p)) > 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU only" in line["error"]
+
+
+def test_step_kernel_name_follows_the_auto_rule():
+    """bench.py names the kernel the library's AUTO rule launches (for the roofline line)."""
+    import sys
+    from types import SimpleNamespace
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import bench
+    big, small, huge = SimpleNamespace(nx=4096, ny=4096), SimpleNamespace(nx=512, ny=512), SimpleNamespace(nx=6528, ny=6528)
+    assert bench.step_kernel_name("f32", big) == "k_collide_advect_sweep"
+    assert bench.step_kernel_name("f64", big) == "k_collide_advect_sweep"
+    assert bench.step_kernel_name("f64", small) == "k_collide_advect_lds"
+    assert bench.step_kernel_name("f32", small) == "k_collide_advect"
+    assert bench.step_kernel_name("f32", huge) == "k_collide_advect"  # distribution above 2 GiB
+    assert bench.step_kernel_name("bf16_dev", huge) == "k_collide_advect_sweep"
