@@ -62,8 +62,10 @@ def test_sizes_and_defaults():
     assert lib.dvbm_num_populations(3) == dvbm.DVBM_EINVAL
 
 
-@pytest.mark.parametrize("field,value", [("nx", 3), ("split", 3), ("gamma", 2.5), ("beta", 0.9), ("Pr", 0.0),
-                                         ("storage", 7), ("tau_ref", -1.0), ("kernel", 4), ("kernel", -1)])
+@pytest.mark.parametrize("field,value", [("nx", 3), ("nx", 0), ("ny", 0), ("ny", -5), ("split", 3), ("gamma", 2.5),
+                                         ("beta", 0.9), ("Pr", 0.0), ("storage", 7), ("tau_ref", -1.0),
+                                         ("kernel", 4), ("kernel", -1), ("dx", 0.0), ("bc_x", 2), ("visc_mode", 2),
+                                         ("ny", 1 << 28)])
 def test_invalid_parameters_rejected_before_any_device_work(field, value):
     from paper_2510_04197_amd import dvbm
     lib = dvbm.load_library()

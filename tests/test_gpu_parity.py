@@ -326,6 +326,20 @@ def test_largest_grid_fp64_sampled():
 
 
 # ---------------------------------------------------------------- errors raised from device checks
+def test_zero_and_negative_step_counts():
+    wl = smooth_random(16, 16, seed=1)
+    s, _ = solver(wl, tau_ref=0.02)
+    X0 = s.store_populations()
+    idx = s.state_index
+    s.step(0)
+    assert s.state_index == idx and torch.equal(s.store_populations(), X0)
+    with pytest.raises(DVBMError) as e:
+        s.step(-1)
+    assert e.value.code == dvbm.DVBM_EINVAL
+    assert torch.equal(s.store_populations(), X0)
+    s.close()
+
+
 def test_nonphysical_initial_state_rejected():
     wl = smooth_random(16, 16, seed=1)
     wl.T[3, 4] = -1.0
