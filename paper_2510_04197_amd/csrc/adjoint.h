@@ -491,6 +491,13 @@ __device__ inline void sweep_adjoint_flux(const typename S::T* __restrict__ stat
   const double kvx = kp.kx * xa;
   const int pl0 = D * Q + a * N1;
   const LT* lp = lam1 + int64_t(pl0) * cells + gx;
+  // stores of lam through one buffer resource per plane (dense rows of nx
+  // values, a plane well below 2 GiB); the stencil-only lanes store to offset
+  // 2^31, which the bounds check discards, so no branch guards the stores
+  // (a branch there makes every store wait for all loads in flight)
+  const uint32_t lrow_bytes = uint32_t(kp.nx) * uint32_t(sizeof(LT));
+  const uint32_t lplane_bytes = uint32_t(cells) * uint32_t(sizeof(LT));
+  const uint32_t lvo_st = own ? uint32_t(x) * uint32_t(sizeof(LT)) : 0x80000000u;
 
   constexpr int NW = D == 0 ? 11 : 4;  // work rows read: 0..9 and 13 (f), 10..13 (g)
   double X[N1][4], Lm[N1][4], p1[N1], p2[N1], gs[N1];
@@ -509,21 +516,31 @@ __device__ inline void sweep_adjoint_flux(const typename S::T* __restrict__ stat
     }
   };
 
+  // the NW work rows of row r (a start-up row reads an edge row and ignores it)
+  auto load_work = [&](double* dst, int r) {
+    const int rr = r < 0 ? 0 : (r >= kp.ny ? kp.ny - 1 : r);
+    const int64_t cc = int64_t(rr) * kp.nx + gx;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const int row = D == 0 ? (k < 10 ? k : N_MOMENTS) : (k < 3 ? 10 + k : N_MOMENTS);
+      dst[k] = work[int64_t(row) * cells + cc];
+    }
+  };
+
   auto step = [&](auto phase, int c) {
     constexpr int P = decltype(phase)::value;
     constexpr int s0 = P, s1 = (P + 1) & 3, s2 = (P + 2) & 3, s3 = (P + 3) & 3;
-    if (c + 3 <= yb + 1) fill(std::integral_constant<int, s3>(), c + 3);
     const bool outrow = c >= ya;
-    // relaxation part: moment cotangents of the cell (row c)
+    // relaxation part: moment cotangents of the cell (row c; a start-up row
+    // reads row 0 and ignores it).  They are loaded before row c+3 is
+    // requested: loads complete in order, so waiting for them then does not
+    // wait for the new row.
     double w[NW];
-    if (outrow) {
-      const int64_t cc = int64_t(c) * kp.nx + gx;
-#pragma unroll
-      for (int k = 0; k < NW; ++k) {
-        const int r = D == 0 ? (k < 10 ? k : N_MOMENTS) : (k < 3 ? 10 + k : N_MOMENTS);
-        w[k] = work[int64_t(r) * cells + cc];
-      }
-    }
+    load_work(w, c);
+    __builtin_amdgcn_sched_barrier(0);  // keep the row-(c+3) loads after these
+    // row c+3 into the slot of row c-1 (past the last needed row, yb+1, a
+    // repeat of that row that is never read)
+    fill(std::integral_constant<int, s3>(), c + 3 <= yb + 1 ? c + 3 : yb + 1);
     const bool last = ZGY && c == kp.ny - 1;
 #pragma unroll
     for (int b = 0; b < N1; ++b) {
@@ -596,7 +613,7 @@ __device__ inline void sweep_adjoint_flux(const typename S::T* __restrict__ stat
       } else {
         out += w[0] + w[1] * xa + w[2] * xb + w[3] * Lm[b][s0];
       }
-      if (own) lam0[int64_t(pl0 + b) * cells + int64_t(c) * kp.nx + x] = LT(out);
+      Buf<LT>::st(plane_rsrc(lam0, pl0 + b, lplane_bytes), uint32_t(c) * lrow_bytes, lvo_st, LT(out));
     }
   };
 

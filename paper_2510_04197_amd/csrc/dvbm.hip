@@ -1045,6 +1045,11 @@ size_t dvbm_adjoint_bytes(const dvbm_params* p) {
 static int adjoint_storage_ok(const dvbm_handle* h, const char* who) {
   if (h->p.storage != DVBM_F64 && h->p.storage != DVBM_F32)
     return fail(DVBM_EINVAL, std::string(who) + ": the adjoint supports f64 and f32 storage");
+  // the flux adjoint stores each cotangent plane through one buffer resource
+  // with 32-bit offsets and discards stores at offset 2^31 (the distribution
+  // limit keeps a float64 plane below 0.6 GiB)
+  if (int64_t(h->p.nx) * h->p.ny * int64_t(sizeof(double)) >= (int64_t(1) << 31))
+    return fail(DVBM_EINVAL, std::string(who) + ": a cotangent plane must stay below 2 GiB");
   return DVBM_OK;
 }
 
