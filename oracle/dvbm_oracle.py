@@ -43,6 +43,11 @@ design notes):
   populations into two ghost layers.
 * ``CONST_MU`` (the paper's fixed dynamic viscosity, Sec. III A 3) gives a
   per-node ``tau_nu = mu / p``; ``CONST_TAU`` keeps ``tau_nu`` fixed.
+* No-slip walls (the thermal Couette case, Sec. IV): the wall lies on the
+  face below row 0 (above row ny-1); the two ghost rows mirror the first two
+  interior rows, ghost ``k`` (k = 1, 2 away from the wall) taking the fields
+  ``rho_G = rho_B, u_G = 2 u_W - u_B, T_G = 2 T_W - T_B`` of interior row
+  ``k`` and the populations ``X^eq(G) + (X_B - X^eq(B))``.
 """
 
 from __future__ import annotations
@@ -58,6 +63,7 @@ D = 2  # physical dimension
 
 PERIODIC = "periodic"
 ZERO_GRADIENT = "zero_gradient"
+WALL = "wall"  # y only: no-slip wall with a given temperature and x velocity
 CONST_MU = "const_mu"
 CONST_TAU = "const_tau"
 
@@ -85,6 +91,8 @@ class Config:
     T_ref: float = 1.0
     beta: float = 1.2
     cfl: float = 0.01
+    wall_T: tuple = (1.0, 1.0)    # bc_y == WALL: temperatures of the lower and upper wall
+    wall_ux: tuple = (0.0, 0.0)   # bc_y == WALL: x velocities of the lower and upper wall
 
     @property
     def Cv(self) -> float:
@@ -438,17 +446,25 @@ def neighbour(n: int, idx: torch.Tensor, bc: str) -> torch.Tensor:
     raise ValueError(bc)
 
 
-def face_values(X: torch.Tensor, vel: torch.Tensor, axis: int, bc: str, beta: float) -> torch.Tensor:
+def face_values(X: torch.Tensor, vel: torch.Tensor, axis: int, bc: str, beta: float, ghosts=None) -> torch.Tensor:
     """NND face values ``X_{k - 1/2}`` for ``k = 0 .. n`` along ``axis`` of ``X`` ([Q, ny, nx]).
 
     Population ``i`` uses the upwind formula of its own velocity component
-    ``vel[i]`` (``>= 0``: left-biased; ``< 0``: right-biased).
+    ``vel[i]`` (``>= 0``: left-biased; ``< 0``: right-biased).  With
+    ``ghosts = (below, above)`` (two layers each, outermost first below,
+    innermost first above) the cells outside ``0 .. n-1`` are those layers.
     """
     n = X.shape[axis]
     k = torch.arange(n + 1)
 
-    def at(off):
-        return X.index_select(axis, neighbour(n, k + off, bc))
+    if ghosts is not None:
+        Xe = torch.cat([ghosts[0], X, ghosts[1]], axis)  # cell c sits at c + 2
+
+        def at(off):
+            return Xe.index_select(axis, k + off + 2)
+    else:
+        def at(off):
+            return X.index_select(axis, neighbour(n, k + off, bc))
 
     Xm2, Xm1, X0, Xp1 = at(-2), at(-1), at(0), at(1)
     pos = Xm1 + limited_increment(Xm1 - Xm2, X0 - Xm1, beta)
@@ -457,10 +473,12 @@ def face_values(X: torch.Tensor, vel: torch.Tensor, axis: int, bc: str, beta: fl
     return torch.where(mask, pos, neg)
 
 
-def advection(X: torch.Tensor, v: torch.Tensor, cfg: Config, dt) -> torch.Tensor:
-    """``-(dt/dV) sum_sigma v_i . n X_i(sigma) dA`` on the uniform Cartesian grid (Sec. III A 1-2)."""
+def advection(X: torch.Tensor, v: torch.Tensor, cfg: Config, dt, ghosts_y=None) -> torch.Tensor:
+    """``-(dt/dV) sum_sigma v_i . n X_i(sigma) dA`` on the uniform Cartesian grid (Sec. III A 1-2).
+
+    ``ghosts_y``: the two ghost rows below and above (walls, see ``wall_ghosts``)."""
     fx = face_values(X, v[:, 0], 2, cfg.bc_x, cfg.beta)  # [Q, ny, nx+1]
-    fy = face_values(X, v[:, 1], 1, cfg.bc_y, cfg.beta)  # [Q, ny+1, nx]
+    fy = face_values(X, v[:, 1], 1, cfg.bc_y, cfg.beta, ghosts_y)  # [Q, ny+1, nx]
     vx = v[:, 0].reshape(-1, 1, 1)
     vy = v[:, 1].reshape(-1, 1, 1)
     div = (vx * (fx[:, :, 1:] - fx[:, :, :-1]) / cfg.dx
@@ -487,12 +505,43 @@ def initial_state(rho, ux, uy, T, cfg: Config):
     return equilibria(rho, u, T, E, cfg)
 
 
+def wall_ghosts(f, g, cfg: Config):
+    """Ghost rows of no-slip walls below row 0 and above row ny-1 (thermal
+    Couette flow, Sec. IV): ghost k (k = 1, 2 rows away from the wall) takes
+    the fields of interior row k, reflected through the wall values,
+    ``rho_G = rho_B``, ``u_G = 2 u_W - u_B``, ``T_G = 2 T_W - T_B``, and the
+    populations ``X^eq(rho_G, u_G, T_G) + (X_B - X^eq(rho_B, u_B, T_B))``.
+    Returns ``((f_below, f_above), (g_below, g_above))``, each [Q, 2, nx]
+    (below: the outer row first; above: the inner row first)."""
+    v, _ = velocity_set(cfg)
+    rho, u, E, T = macroscopic(f, g, v, cfg)
+    feq, geq = equilibria(rho, u, T, E, cfg)
+
+    def ghost(row, wall):
+        uW = torch.tensor([cfg.wall_ux[wall], 0.0], dtype=DT)
+        rG, uG, TG = rho[row], 2.0 * uW - u[row], 2.0 * cfg.wall_T[wall] - T[row]
+        fG, gG = equilibria(rG, uG, TG, total_energy(rG, uG, TG, cfg), cfg)
+        return fG + (f[:, row] - feq[:, row]), gG + (g[:, row] - geq[:, row])
+
+    ny = f.shape[1]
+    b2, b1 = ghost(1, 0), ghost(0, 0)            # rows -2, -1
+    a1, a2 = ghost(ny - 1, 1), ghost(ny - 2, 1)  # rows ny, ny+1
+    fb = torch.stack([b2[0], b1[0]], 1)
+    gb = torch.stack([b2[1], b1[1]], 1)
+    fa = torch.stack([a1[0], a2[0]], 1)
+    ga = torch.stack([a1[1], a2[1]], 1)
+    return (fb, fa), (gb, ga)
+
+
 def step(f, g, cfg: Config, dt, tau_ref=None, Pr=None):
     """One forward-Euler update of Eq. (finalDiscretePDE) for both distributions."""
     v, _ = velocity_set(cfg)
     cf, cg = collision(f, g, cfg, dt, tau_ref, Pr)
-    f_new = f + advection(f, v, cfg, dt) + cf
-    g_new = g + advection(g, v, cfg, dt) + cg
+    gf = gg = None
+    if cfg.bc_y == WALL:
+        gf, gg = wall_ghosts(f, g, cfg)
+    f_new = f + advection(f, v, cfg, dt, gf) + cf
+    g_new = g + advection(g, v, cfg, dt, gg) + cg
     return f_new, g_new
 
 
