@@ -60,7 +60,16 @@ extern "C" {
 #define DVBM_ESTIFF (-4) /* dt / tau_1 > 2 for the initial state */
 
 enum dvbm_storage { DVBM_F64 = 0, DVBM_F32 = 1, DVBM_BF16_DEV = 2, DVBM_FP16_DEV = 3 };
-enum dvbm_bc { DVBM_PERIODIC = 0, DVBM_ZERO_GRADIENT = 1 };
+/* Boundaries: periodic; zero-gradient (two ghost layers copy the nearest
+ * interior cell); DVBM_WALL (bc_y only): no-slip walls on the faces below row
+ * 0 and above row ny-1 with temperatures wall_T and x velocities wall_ux
+ * (thermal Couette flow, Sec. IV).  The wall's two ghost rows take the fields
+ * of the first two interior rows reflected through the wall values,
+ * rho_G = rho_B, u_G = 2 u_W - u_B, T_G = 2 T_W - T_B, and the populations
+ * X^eq(G) + (X_B - X^eq(B)).  Walls run on the per-cell kernel, need the
+ * larger workspace dvbm_workspace_bytes() reports for them, and have no
+ * adjoint (EINVAL). */
+enum dvbm_bc { DVBM_PERIODIC = 0, DVBM_ZERO_GRADIENT = 1, DVBM_WALL = 2 };
 enum dvbm_visc { DVBM_CONST_MU = 0, DVBM_CONST_TAU = 1 };
 /* Step kernel (all compute the same update; the choice only affects speed):
  * AUTO picks the column sweep on grids of at least 3 * 2^18 cells (for
@@ -96,6 +105,8 @@ typedef struct dvbm_params {
   double beta;         /* limiter parameter in [1, 2] */
   double cfl;          /* > 0; used when dt <= 0 */
   double dt;           /* > 0 overrides dt = cfl * min(dx, dy) / max(|u| + sqrt(gamma R T)) */
+  double wall_T[2];    /* bc_y == DVBM_WALL: temperature (> 0) of the lower and the upper wall (default 1) */
+  double wall_ux[2];   /* bc_y == DVBM_WALL: x velocity of the lower and the upper wall (default 0) */
 } dvbm_params;
 
 typedef struct dvbm_handle dvbm_handle;
@@ -117,7 +128,8 @@ int64_t dvbm_pitch(const dvbm_params* p);
 /* Bytes of ONE population buffer (f and g) for these parameters; 0 if invalid. */
 size_t dvbm_buffer_bytes(const dvbm_params* p);
 
-/* Bytes of the caller-provided device workspace (reduction partials). */
+/* Bytes of the caller-provided device workspace (reduction partials, and the
+ * wall ghost rows when bc_y == DVBM_WALL). */
 size_t dvbm_workspace_bytes(const dvbm_params* p);
 
 /*

@@ -43,6 +43,8 @@ static_assert(ADJ_RELAX_BLOCKS <= RED_BLOCKS, "adjoint partials exceed the works
 // workspace layout (doubles): [0, 4 RED_BLOCKS) block partials, then the
 // final reductions, then (at WS_TICKET) the adjoint's block counter
 constexpr int WS_TICKET = 4 * RED_BLOCKS + 32;
+// then, with walls in y, the 4 ghost rows of every population plane
+constexpr int WS_GHOST = 4 * RED_BLOCKS + 64;
 #ifndef DVBM_CELL_TX
 #define DVBM_CELL_TX 64
 #endif
@@ -85,13 +87,14 @@ __device__ inline void tile_of_block(int w, int nbx, int nby, int& bx, int& by) 
 // ------------------------------------------------------------ fused step
 template <int SPLIT, class S, int BCX, int BCY, int PRM>
 __global__ __launch_bounds__(CELL_TX* CELL_TY) void k_collide_advect(const typename S::T* __restrict__ src,
-                                                                     typename S::T* __restrict__ dst, KParams kp) {
+                                                                     typename S::T* __restrict__ dst, KParams kp,
+                                                                     const typename S::T* __restrict__ ghost) {
   int bx, by;
   tile_of_block(blockIdx.x, (kp.nx + CELL_TX - 1) / CELL_TX, (kp.ny + CELL_TY - 1) / CELL_TY, bx, by);
   const int x = bx * CELL_TX + threadIdx.x;
   const int y = by * CELL_TY + threadIdx.y;
   if (x >= kp.nx || y >= kp.ny) return;
-  cell_update<SPLIT, S, BCX, BCY, PRM>(src, dst, kp, x, y);
+  cell_update<SPLIT, S, BCX, BCY, PRM>(src, dst, kp, x, y, ghost);
 }
 
 template <int SPLIT, class S, int BCX, int BCY, int PRM>
@@ -226,6 +229,48 @@ __device__ inline double decode_one(const typename S::T v, int d, int i, const K
   const double w = weight<SPLIT>(i);
   const double r = d == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i);
   return w * (r + double(S::raw(v)));
+}
+
+// ------------------------------------------------------------ no-slip walls
+// Ghost rows of the walls below row 0 and above row ny-1 (thermal Couette
+// flow, Sec. IV): the ghost row k = 1, 2 rows away from a wall takes the
+// fields of interior row k reflected through the wall values (rho_G = rho_B,
+// u_G = 2 u_W - u_B, T_G = 2 T_W - T_B) and the populations
+// X^eq(G) + (X_B - X^eq(B)), encoded in the storage format.
+// ghost[(d Q + i) 4 + r][x] (row stride pitch), r = 0..3 for the rows -2, -1,
+// ny, ny+1; one thread per (x, r).
+template <int SPLIT, class S>
+__global__ __launch_bounds__(256) void k_wall_ghosts(const typename S::T* __restrict__ src,
+                                                     typename S::T* __restrict__ ghost, KParams kp) {
+  constexpr int N1 = Set<SPLIT>::N1;
+  constexpr int Q = Set<SPLIT>::Q;
+  using C = typename S::C;
+  const int t = int(blockIdx.x * blockDim.x + threadIdx.x);
+  if (t >= 4 * kp.nx) return;
+  const int r = t / kp.nx, x = t - r * kp.nx;
+  const int yb = r == 0 ? 1 : (r == 1 ? 0 : (r == 2 ? kp.ny - 1 : kp.ny - 2));
+  const int wall = r < 2 ? 0 : 1;
+  const int64_t off = int64_t(yb) * kp.pitch + x;
+  double f[Q], g[Q];
+  for (int i = 0; i < Q; ++i) {
+    f[i] = decode_one<SPLIT, S>(src[int64_t(i) * kp.plane + off], 0, i, kp);
+    g[i] = decode_one<SPLIT, S>(src[int64_t(Q + i) * kp.plane + off], 1, i, kp);
+  }
+  // the boundary cell's rho, u, T (Eqs. eq_quadratur1-3 and eq:Total_energy_MB)
+  const NodeMoments m = node_moments<N1>(f, g);
+  const double c = sqrt(kp.c2);
+  const double rho = m.rho, ux = c * m.jx / rho, uy = c * m.jy / rho;
+  const double E = SPLIT == 2 ? m.g0 + 0.5 * kp.c2 * (m.pxx + m.pyy) : m.g0;
+  const double T = (E / rho - 0.5 * (ux * ux + uy * uy)) * kp.inv_Cv;
+  double feqB[Q], geqB[Q], feqG[Q], geqG[Q];
+  equilibrium_cell<SPLIT, double>(rho, ux, uy, T, kp, feqB, geqB);
+  equilibrium_cell<SPLIT, double>(rho, 2.0 * kp.wall_ux[wall] - ux, -uy, 2.0 * kp.wall_T[wall] - T, kp, feqG, geqG);
+  for (int i = 0; i < Q; ++i) {
+    const double w = weight<SPLIT>(i);
+    ghost[(int64_t(i) * 4 + r) * kp.pitch + x] = S::enc(C(feqG[i] + (f[i] - feqB[i])), C(1.0 / w), C(1.0));
+    ghost[(int64_t(Q + i) * 4 + r) * kp.pitch + x] =
+        S::enc(C(geqG[i] + (g[i] - geqB[i])), C(1.0 / w), C(g_ref_over_w<SPLIT>(kp, i)));
+  }
 }
 
 template <int SPLIT, class S>
@@ -499,8 +544,14 @@ std::string check_params(const dvbm_params* p) {
   if (p->split != 1 && p->split != 2) return "split must be 1 or 2";
   if (p->storage < DVBM_F64 || p->storage > DVBM_FP16_DEV) return "unknown storage";
   if ((p->bc_x != DVBM_PERIODIC && p->bc_x != DVBM_ZERO_GRADIENT) ||
-      (p->bc_y != DVBM_PERIODIC && p->bc_y != DVBM_ZERO_GRADIENT))
-    return "unknown boundary condition";
+      (p->bc_y != DVBM_PERIODIC && p->bc_y != DVBM_ZERO_GRADIENT && p->bc_y != DVBM_WALL))
+    return "unknown boundary condition (walls are supported in y only)";
+  if (p->bc_y == DVBM_WALL) {
+    if (!(p->wall_T[0] > 0) || !(p->wall_T[1] > 0)) return "wall temperatures must be > 0";
+    if (!std::isfinite(p->wall_ux[0]) || !std::isfinite(p->wall_ux[1])) return "wall velocities must be finite";
+    if (p->kernel == DVBM_KERNEL_SWEEP || p->kernel == DVBM_KERNEL_TILE)
+      return "walls are supported by the per-cell kernel only (kernel AUTO or CELL)";
+  }
   if (p->visc_mode != DVBM_CONST_MU && p->visc_mode != DVBM_CONST_TAU) return "unknown visc_mode";
   if (p->kernel < DVBM_KERNEL_AUTO || p->kernel > DVBM_KERNEL_TILE) return "unknown kernel";
   if (!(p->dx > 0) || !(p->dy > 0)) return "dx, dy must be > 0";
@@ -563,6 +614,10 @@ KParams make_kparams(const dvbm_params& p, double dt) {
     k.gr0 = k.Cv * p.T_ref;
     k.gr1 = 0.5 * k.c2;
   }
+  for (int w = 0; w < 2; ++w) {
+    k.wall_T[w] = p.wall_T[w];
+    k.wall_ux[w] = p.wall_ux[w];
+  }
   return k;
 }
 
@@ -602,6 +657,7 @@ namespace dvbm_launch {
 
 // The kernel a handle's steps use (the AUTO rule of dvbm_kernel).
 inline int step_kernel(const dvbm_handle* h) {
+  if (h->p.bc_y == DVBM_WALL) return DVBM_KERNEL_CELL;
   if (h->p.kernel != DVBM_KERNEL_AUTO) return h->p.kernel;
   const bool big = int64_t(h->p.nx) * h->p.ny >= SWEEP_MIN_CELLS;
   if (h->p.storage == DVBM_F64) return DVBM_SWEEP && big ? DVBM_KERNEL_SWEEP : DVBM_KERNEL_TILE;
@@ -616,6 +672,15 @@ void launch_step_pr(const dvbm_handle* h, const void* src, void* dst) {
   using T = typename S::T;
   const T* s = static_cast<const T*>(src);
   T* d = static_cast<T*>(dst);
+  if constexpr (BCY == BC_WALL) {
+    T* gh = reinterpret_cast<T*>(h->ws + WS_GHOST);
+    hipLaunchKernelGGL((k_wall_ghosts<SPLIT, S>), dim3((4 * h->p.nx + 255) / 256), dim3(256), 0, h->stream, s, gh,
+                       h->kp);
+    const dim3 grid(((h->p.nx + CELL_TX - 1) / CELL_TX) * ((h->p.ny + CELL_TY - 1) / CELL_TY));
+    hipLaunchKernelGGL((k_collide_advect<SPLIT, S, BCX, BCY, PRM>), grid, dim3(CELL_TX, CELL_TY), 0, h->stream, s, d,
+                       h->kp, static_cast<const T*>(gh));
+    return;
+  } else {
   const int kern_id = step_kernel(h);
   if (kern_id == DVBM_KERNEL_TILE) {
     const dim3 grid(((h->p.nx + TILE_TX - 1) / TILE_TX) * ((h->p.ny + TILE_TY - 1) / TILE_TY));
@@ -639,7 +704,8 @@ void launch_step_pr(const dvbm_handle* h, const void* src, void* dst) {
   }
   const dim3 grid(((h->p.nx + CELL_TX - 1) / CELL_TX) * ((h->p.ny + CELL_TY - 1) / CELL_TY));
   hipLaunchKernelGGL((k_collide_advect<SPLIT, S, BCX, BCY, PRM>), grid, dim3(CELL_TX, CELL_TY), 0, h->stream, s, d,
-                     h->kp);
+                     h->kp, static_cast<const T*>(nullptr));
+  }
 }
 
 template <int SPLIT, class S, int BCX, int BCY>
@@ -656,7 +722,12 @@ void launch_step_bc(const dvbm_handle* h, const void* src, void* dst) {
 template <int SPLIT, class S>
 void step(const dvbm_handle* h, const void* src, void* dst) {
   const int bx = h->p.bc_x, by = h->p.bc_y;
-  if (bx == DVBM_PERIODIC && by == DVBM_PERIODIC)
+  if (by == DVBM_WALL) {
+    if (bx == DVBM_PERIODIC)
+      launch_step_bc<SPLIT, S, BC_PERIODIC, BC_WALL>(h, src, dst);
+    else
+      launch_step_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_WALL>(h, src, dst);
+  } else if (bx == DVBM_PERIODIC && by == DVBM_PERIODIC)
     launch_step_bc<SPLIT, S, BC_PERIODIC, BC_PERIODIC>(h, src, dst);
   else if (bx == DVBM_ZERO_GRADIENT && by == DVBM_PERIODIC)
     launch_step_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_PERIODIC>(h, src, dst);
@@ -868,6 +939,8 @@ void dvbm_params_default(dvbm_params* p) {
   p->beta = 1.2;
   p->cfl = 0.01;
   p->dt = 0.0;
+  p->wall_T[0] = p->wall_T[1] = 1.0;
+  p->wall_ux[0] = p->wall_ux[1] = 0.0;
 }
 
 int dvbm_num_populations(int32_t split) {
@@ -907,8 +980,10 @@ size_t dvbm_buffer_bytes(const dvbm_params* p) {
 }
 
 size_t dvbm_workspace_bytes(const dvbm_params* p) {
-  (void)p;
-  return size_t(RED_BLOCKS * 4 + 64) * sizeof(double);
+  size_t n = size_t(WS_GHOST) * sizeof(double);
+  if (p && p->bc_y == DVBM_WALL && check_params(p).empty())  // 4 ghost rows of each of the 2Q planes
+    n += size_t(2) * (p->split == 1 ? 16 : 25) * 4 * size_t(dvbm_pitch(p)) * storage_bytes(p->storage);
+  return n;
 }
 
 int dvbm_init(const dvbm_params* p, const double* rho, const double* ux, const double* uy, const double* T,
@@ -1045,6 +1120,7 @@ size_t dvbm_adjoint_bytes(const dvbm_params* p) {
 static int adjoint_storage_ok(const dvbm_handle* h, const char* who) {
   if (h->p.storage != DVBM_F64 && h->p.storage != DVBM_F32)
     return fail(DVBM_EINVAL, std::string(who) + ": the adjoint supports f64 and f32 storage");
+  if (h->p.bc_y == DVBM_WALL) return fail(DVBM_EINVAL, std::string(who) + ": the adjoint does not support walls");
   // the flux adjoint stores each cotangent plane through one buffer resource
   // with 32-bit offsets and discards stores at offset 2^31 (the distribution
   // limit keeps a float64 plane below 0.6 GiB)

@@ -17,7 +17,7 @@
 namespace dvbm {
 
 enum { PR_UNIT = 0, PR_LOW = 1, PR_HIGH = 2 };
-enum { BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1 };
+enum { BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1, BC_WALL = 2 };
 
 template <int SPLIT>
 struct Set {
@@ -39,6 +39,8 @@ struct KParams {
   double Pr;
   double beta2;          // 2 beta
   double gr0, gr1;       // rest g per weight: gr0 + gr1 (|xi|^2 - 2)
+  double wall_T[2];      // no-slip walls in y (below row 0, above row ny-1): temperature
+  double wall_ux[2];     // and x velocity of each wall (physical units)
 };
 
 // ------------------------------------------------------------ storage formats

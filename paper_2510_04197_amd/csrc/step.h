@@ -106,7 +106,8 @@ __device__ inline void static_for(F&& f) {
 // read through the vector L1/L2 caches.
 template <int SPLIT, class S, int BCX, int BCY, int PRM>
 __device__ inline void cell_update(const typename S::T* __restrict__ src, typename S::T* __restrict__ dst,
-                                   const KParams& kp, int x, int y) {
+                                   const KParams& kp, int x, int y,
+                                   const typename S::T* __restrict__ ghost = nullptr) {
   using R = typename S::C;
   using T = typename S::T;
   constexpr int N1 = Set<SPLIT>::N1;
@@ -179,12 +180,23 @@ __device__ inline void cell_update(const typename S::T* __restrict__ src, typena
       else if (xa < 0.0)
         div += kx * R(xa) * dface_neg(S::raw(Buf<T>::ld(pl, so, oxm1)), c0, S::raw(Buf<T>::ld(pl, so, oxp1)),
                                         S::raw(Buf<T>::ld(pl, so, oxp2)), beta2);
+      // value of the plane at row y + dy; with walls, rows outside the domain
+      // come from the ghost rows (ghost[(d Q + i) 4 + r][x], r = 0..3 for the
+      // rows -2, -1, ny, ny+1)
+      auto ly = [&](uint32_t off, int dy) -> R {
+        if constexpr (BCY == BC_WALL) {
+          const int yy = y + dy;
+          if (yy < 0 || yy >= kp.ny) {
+            const int gr = yy < 0 ? yy + 2 : yy - kp.ny + 2;
+            return S::raw(ghost[(int64_t(d * Q + i) * 4 + gr) * kp.pitch + x]);
+          }
+        }
+        return S::raw(Buf<T>::ld(pl, so, off));
+      };
       if (xb > 0.0)
-        div += ky * R(xb) * dface_pos(S::raw(Buf<T>::ld(pl, so, oym2)), S::raw(Buf<T>::ld(pl, so, oym1)), c0,
-                                        S::raw(Buf<T>::ld(pl, so, oyp1)), beta2);
+        div += ky * R(xb) * dface_pos(ly(oym2, -2), ly(oym1, -1), c0, ly(oyp1, 1), beta2);
       else if (xb < 0.0)
-        div += ky * R(xb) * dface_neg(S::raw(Buf<T>::ld(pl, so, oym1)), c0, S::raw(Buf<T>::ld(pl, so, oyp1)),
-                                        S::raw(Buf<T>::ld(pl, so, oyp2)), beta2);
+        div += ky * R(xb) * dface_neg(ly(oym1, -1), c0, ly(oyp1, 1), ly(oyp2, 2), beta2);
       const double w = weight<SPLIT>(i);
       const R rr = S::dev ? R(d == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i)) : R(0);
       const R xnew = X[d][i] - (S::dev ? R(w) * div : div);

@@ -24,7 +24,7 @@ DVBM_ENAN = -3
 DVBM_ESTIFF = -4
 
 STORAGE = {"f64": 0, "f32": 1, "bf16_dev": 2, "fp16_dev": 3}
-BC = {"periodic": 0, "zero_gradient": 1}
+BC = {"periodic": 0, "zero_gradient": 1, "wall": 2}
 VISC = {"const_mu": 0, "const_tau": 1}
 KERNEL = {"auto": 0, "cell": 1, "sweep": 2, "tile": 3}
 
@@ -41,6 +41,7 @@ class Params(ctypes.Structure):
         ("visc_mode", ctypes.c_int32), ("kernel", ctypes.c_int32),
         ("dx", _D), ("dy", _D), ("R", _D), ("gamma", _D), ("Pr", _D), ("tau_ref", _D),
         ("p_ref", _D), ("T_ref", _D), ("beta", _D), ("cfl", _D), ("dt", _D),
+        ("wall_T", _D * 2), ("wall_ux", _D * 2),
     ]
 
 
@@ -110,7 +111,7 @@ def num_populations(split: int) -> int:
 
 def make_params(nx, ny, split=2, storage="f32", bc_x="periodic", bc_y="periodic", visc_mode="const_mu",
                 dx=None, dy=None, R=1.0, gamma=1.4, Pr=0.71, tau_ref=5e-5, p_ref=1.0, T_ref=1.0,
-                beta=1.2, cfl=0.01, dt=0.0, kernel="auto") -> Params:
+                beta=1.2, cfl=0.01, dt=0.0, kernel="auto", wall_T=(1.0, 1.0), wall_ux=(0.0, 0.0)) -> Params:
     lib = load_library()
     p = Params()
     lib.dvbm_params_default(ctypes.byref(p))
@@ -124,6 +125,8 @@ def make_params(nx, ny, split=2, storage="f32", bc_x="periodic", bc_y="periodic"
     p.R, p.gamma, p.Pr, p.tau_ref, p.p_ref, p.T_ref = map(float, (R, gamma, Pr, tau_ref, p_ref, T_ref))
     p.beta, p.cfl, p.dt = float(beta), float(cfl), float(dt)
     p.kernel = KERNEL[kernel] if isinstance(kernel, str) else int(kernel)
+    p.wall_T[0], p.wall_T[1] = map(float, wall_T)      # bc_y == "wall": lower, upper wall
+    p.wall_ux[0], p.wall_ux[1] = map(float, wall_ux)
     return p
 
 
