@@ -175,24 +175,29 @@ class Solver:
                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self.handle = h
 
+    def _h(self):
+        if not getattr(self, "handle", None):
+            raise DVBMError(DVBM_EINVAL, "the solver is closed")
+        return self.handle
+
     # ------------------------------------------------------------------ stepping
     def step(self, nsteps: int = 1):
-        _check(self.lib.dvbm_step(self.handle, int(nsteps)))
+        _check(self.lib.dvbm_step(self._h(), int(nsteps)))
 
     def step_from(self, src: torch.Tensor, dst: torch.Tensor):
         """One step from the population buffer ``src`` into ``dst``; the solver's own state is unchanged."""
-        _check(self.lib.dvbm_step_from(self.handle, _ptr(src), _ptr(dst)))
+        _check(self.lib.dvbm_step_from(self._h(), _ptr(src), _ptr(dst)))
 
     @property
     def dt(self) -> float:
-        return float(self.lib.dvbm_get_dt(self.handle))
+        return float(self.lib.dvbm_get_dt(self._h()))
 
     @property
     def state_index(self) -> int:
-        return int(self.lib.dvbm_state_index(self.handle))
+        return int(self.lib.dvbm_state_index(self._h()))
 
     def set_state_index(self, idx: int):
-        _check(self.lib.dvbm_set_state_index(self.handle, int(idx)))
+        _check(self.lib.dvbm_set_state_index(self._h(), int(idx)))
 
     @property
     def state_buffer(self) -> torch.Tensor:
@@ -207,7 +212,7 @@ class Solver:
                 out[k] = torch.empty((ny, nx), dtype=torch.float64, device=self.device)
         ptrs = [_ptr(out[k]) if fields else None for k in ("rho", "ux", "uy", "T")]
         s = (ctypes.c_double * 4)()
-        _check(self.lib.dvbm_moments(self.handle, *ptrs, s if sums else None))
+        _check(self.lib.dvbm_moments(self._h(), *ptrs, s if sums else None))
         if sums:
             out["sums"] = np.array(s[:])
         return out
@@ -217,12 +222,12 @@ class Solver:
         X = _dev_f64(X, self.device)
         if tuple(X.shape) != (2, self.Q, self.params.ny, self.params.nx):
             raise ValueError("populations must have shape (2, Q, ny, nx)")
-        _check(self.lib.dvbm_load_populations(self.handle, _ptr(X)))
+        _check(self.lib.dvbm_load_populations(self._h(), _ptr(X)))
         self.stream.synchronize()
 
     def store_populations(self) -> torch.Tensor:
         X = torch.empty((2, self.Q, self.params.ny, self.params.nx), dtype=torch.float64, device=self.device)
-        _check(self.lib.dvbm_store_populations(self.handle, _ptr(X)))
+        _check(self.lib.dvbm_store_populations(self._h(), _ptr(X)))
         self.stream.synchronize()
         return X
 
@@ -243,14 +248,14 @@ class Solver:
             nbytes = self.lib.dvbm_adjoint_work_bytes(ctypes.byref(self.params))
             self._adj_work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         fn = self.lib.dvbm_adjoint_step if lam.dtype == torch.float64 else self.lib.dvbm_adjoint_step_f32
-        _check(fn(self.handle, _ptr(state), _ptr(lam_next), _ptr(lam), _ptr(dparams) if dparams is not None else None,
+        _check(fn(self._h(), _ptr(state), _ptr(lam_next), _ptr(lam), _ptr(dparams) if dparams is not None else None,
                   _ptr(self._adj_work)))
 
     def adjoint_moments(self, state: torch.Tensor, d_rho=None, d_ux=None, d_uy=None, d_T=None) -> torch.Tensor:
         """Cotangent of the populations of ``state`` from cotangents of its fields."""
         lam = self.new_cotangent()
         cot = [None if a is None else _dev_f64(a, self.device) for a in (d_rho, d_ux, d_uy, d_T)]
-        _check(self.lib.dvbm_adjoint_moments(self.handle, _ptr(state), *[_ptr(a) if a is not None else None
+        _check(self.lib.dvbm_adjoint_moments(self._h(), _ptr(state), *[_ptr(a) if a is not None else None
                                                                           for a in cot], _ptr(lam)))
         self._keep = cot
         return lam
@@ -260,7 +265,7 @@ class Solver:
         fields = [_dev_f64(a, self.device) for a in (rho, ux, uy, T)]
         names = ("rho", "ux", "uy", "T")
         outs = {k: torch.zeros_like(fields[0]) for k in which}
-        _check(self.lib.dvbm_adjoint_init(self.handle, _ptr(lam0), *[_ptr(f) for f in fields],
+        _check(self.lib.dvbm_adjoint_init(self._h(), _ptr(lam0), *[_ptr(f) for f in fields],
                                           *[_ptr(outs[k]) if k in outs else None for k in names]))
         self.stream.synchronize()
         return outs

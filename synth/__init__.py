@@ -12,6 +12,7 @@ from .fields import (  # noqa: F401
     shear_wave,
     shock_vortex,
     smooth_random,
+    sod_tube,
     thermal_wave,
     thermal_wave_1d,
     rankine_hugoniot,

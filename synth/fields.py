@@ -247,3 +247,19 @@ def smooth_random(nx: int, ny: int, seed: int = 0, amp_rho: float = 0.05, amp_u:
     uy = mean_u[1] + field_(amp_u)
     T = 1.0 + field_(amp_T)
     return Workload("smooth_random", rho, ux, uy, T, L, Ly, {})
+
+
+def sod_tube(nx: int = 1024, ny: int = 4, R: float = 1.0) -> Workload:
+    """Sod shock tube (Sec. IV, conservation): (rho, p, u_x) = (1, 1, 0) for
+    0 <= x <= 0.5 and (0.125, 0.1, 0) for 0.5 < x <= 1, on the extended
+    periodic domain x in [-0.5, 1.5] (each state continued by 0.5 on its own
+    side, so the second interface, at the periodic seam, stays 0.5 away from
+    [0, 1]); nx cells over the length 2, T = p / (rho R)."""
+    x = _centres(nx, 2.0) - 0.5
+    left = x <= 0.5
+    rho1 = np.where(left, 1.0, 0.125)
+    p1 = np.where(left, 1.0, 0.1)
+    rho = np.repeat(rho1[None, :], ny, 0)
+    T = np.repeat((p1 / (rho1 * R))[None, :], ny, 0)
+    zero = np.zeros((ny, nx))
+    return Workload("sod_tube", rho, zero.copy(), zero.copy(), T, 2.0, 2.0 * ny / nx)

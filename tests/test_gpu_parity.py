@@ -18,7 +18,7 @@ import torch
 
 from oracle import dvbm_oracle as O
 from paper_2510_04197_amd import DVBMError, Solver, dvbm, make_params
-from synth import isentropic_vortex, shear_wave, shock_vortex, smooth_random, thermal_wave, uniform
+from synth import isentropic_vortex, shear_wave, shock_vortex, smooth_random, sod_tube, thermal_wave, uniform
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -380,6 +380,57 @@ def test_thermal_couette_steady_profile(split, Pr):
     assert err < (0.03 if (split == 1 and Pr == 2.0) else 0.01)
 
 
+# ---------------------------------------------------------------- Sod shock tube (Sec. IV, conservation)
+@pytest.mark.parametrize("split", (1, 2))
+@pytest.mark.parametrize("Pr", (0.5, 1.0, 2.0))
+def test_sod_tube_matches_oracle(split, Pr):
+    """The Sod tube's discontinuities put the limiter on all of its branches:
+    128 x 4 cells of the extended periodic domain, 20 steps, FP64."""
+    wl = sod_tube(128, 4)
+    s, p = solver(wl, split=split, storage="f64", Pr=Pr, tau_ref=5e-4)
+    cfg = oracle_cfg(p)
+    f0, g0 = oracle_state(s)
+    s.step(20)
+    f, g = oracle_state(s)
+    fo, go = O.run(f0, g0, cfg, s.dt, 20)
+    assert rel(f, fo) < 1e-12 and rel(g, go) < 1e-12
+    assert rel(f - f0, fo - f0) < 1e-9 and rel(g - g0, go - g0) < 1e-9
+
+
+@pytest.mark.parametrize("split", (1, 2))
+@pytest.mark.parametrize("Pr", (0.5, 1.0, 2.0))
+def test_sod_tube_conservation(split, Pr):
+    """The paper's conservation case: 1024 x 4 cells of x in [-0.5, 1.5],
+    CFL 0.01, mu = 5e-5, FP64 storage, run to t = 0.2.  Total mass and energy
+    (float64 sums over the domain) change by rounding only (below 2^-53 per
+    step; measured 1e-14 to 5e-13 over 12116 steps), the x momentum stays at
+    rounding level, and the density on [0, 1] is within 2 % (relative L1) of
+    the exact Riemann solution of the Euler equations."""
+    wl = sod_tube(1024, 4)
+    s, p = solver(wl, split=split, storage="f64", Pr=Pr, tau_ref=5e-5)
+    m0 = s.moments(fields=False, sums=True)["sums"]
+    dt = s.dt
+    n = int(round(0.2 / dt))
+    s.step(n)
+    out = s.moments(fields=True, sums=True)
+    m1 = out["sums"]
+    s.close()
+    eps = 2.0 ** -53
+    # density on [0, 1] against the exact Riemann solution (Euler level)
+    x = (np.arange(1024) + 0.5) * (2.0 / 1024) - 0.5
+    sel = (x >= 0.0) & (x <= 1.0)
+    rho = out["rho"].cpu().numpy()[0, sel]
+    ex = riemann_density(x[sel] - 0.5, n * dt, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 1.4)
+    l1 = float(np.abs(rho - ex).mean() / np.abs(ex).mean())
+    print(f"[sod] split {split} Pr {Pr}: {n} steps, mass {abs(m1[0] / m0[0] - 1):.2e}, "
+          f"energy {abs(m1[3] / m0[3] - 1):.2e}, momentum {abs(m1[1]) / m0[0]:.2e}, density L1 vs Riemann {l1:.2e}",
+          flush=True)
+    assert abs(m1[0] / m0[0] - 1) < eps * n
+    assert abs(m1[3] / m0[3] - 1) < eps * n
+    assert abs(m1[1]) < eps * n * m0[0]
+    assert l1 < 0.02
+
+
 # ---------------------------------------------------------------- errors raised from device checks
 def test_zero_and_negative_step_counts():
     wl = smooth_random(16, 16, seed=1)
@@ -448,3 +499,64 @@ def test_vortex_1024_fp32_vs_fp64_300_steps():
         assert rel(a, b) < 1e-5, k
         pool = torch.nn.functional.avg_pool2d
         assert rel(pool(a[None, None], 8), pool(b[None, None], 8)) < 1e-5, k
+
+
+def riemann_density(x, t, left, right, gamma):
+    """Exact density of the 1-D Euler Riemann problem for an ideal gas at time
+    t, interface at x = 0 (states (rho, u, p)): the star pressure from the
+    shock / rarefaction pressure functions by Newton iteration, then the wave
+    fan sampled at x / t (textbook construction, e.g. Toro, ch. 4)."""
+    rl, ul, pl = left
+    rr, ur, pr = right
+    g1, g2 = (gamma - 1) / (2 * gamma), (gamma + 1) / (2 * gamma)
+    cl, cr = math.sqrt(gamma * pl / rl), math.sqrt(gamma * pr / rr)
+
+    def fk(p, rk, pk, ck):
+        if p > pk:  # shock
+            a, b = 2 / ((gamma + 1) * rk), (gamma - 1) / (gamma + 1) * pk
+            q = math.sqrt(a / (p + b))
+            return (p - pk) * q, q * (1 - 0.5 * (p - pk) / (p + b))
+        # rarefaction
+        return 2 * ck / (gamma - 1) * ((p / pk) ** g1 - 1), (p / pk) ** (-g2) / (rk * ck)
+
+    p = 0.5 * (pl + pr)
+    for _ in range(100):
+        f1, d1 = fk(p, rl, pl, cl)
+        f2, d2 = fk(p, rr, pr, cr)
+        step = (f1 + f2 + ur - ul) / (d1 + d2)
+        p = max(p - step, 1e-12)
+        if abs(step) < 1e-14 * p:
+            break
+    us = 0.5 * (ul + ur) + 0.5 * (fk(p, rr, pr, cr)[0] - fk(p, rl, pl, cl)[0])
+    out = np.empty_like(x)
+    for k, xk in enumerate(x):
+        s = xk / t
+        if s <= us:  # left of the contact
+            if p > pl:
+                sl = ul - cl * math.sqrt(g2 * p / pl + g1)
+                out[k] = rl if s < sl else rl * ((p / pl + (gamma - 1) / (gamma + 1)) /
+                                               ((gamma - 1) / (gamma + 1) * p / pl + 1))
+            else:
+                shl, cs = ul - cl, cl * (p / pl) ** g1
+                stl = us - cs
+                if s < shl:
+                    out[k] = rl
+                elif s > stl:
+                    out[k] = rl * (p / pl) ** (1 / gamma)
+                else:
+                    out[k] = rl * (2 / (gamma + 1) + (gamma - 1) / ((gamma + 1) * cl) * (ul - s)) ** (2 / (gamma - 1))
+        else:
+            if p > pr:
+                sr = ur + cr * math.sqrt(g2 * p / pr + g1)
+                out[k] = rr if s > sr else rr * ((p / pr + (gamma - 1) / (gamma + 1)) /
+                                               ((gamma - 1) / (gamma + 1) * p / pr + 1))
+            else:
+                shr, cs = ur + cr, cr * (p / pr) ** g1
+                str_ = us + cs
+                if s > shr:
+                    out[k] = rr
+                elif s < str_:
+                    out[k] = rr * (p / pr) ** (1 / gamma)
+                else:
+                    out[k] = rr * (2 / (gamma + 1) - (gamma - 1) / ((gamma + 1) * cr) * (ur - s)) ** (2 / (gamma - 1))
+    return out
