@@ -7,6 +7,7 @@ arithmetic: no populations, moments, equilibria or fluxes.
 
 from .fields import (  # noqa: F401
     Workload,
+    acoustic_wave,
     gaussian_bump,
     isentropic_vortex,
     shear_wave,

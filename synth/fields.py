@@ -263,3 +263,17 @@ def sod_tube(nx: int = 1024, ny: int = 4, R: float = 1.0) -> Workload:
     T = np.repeat((p1 / (rho1 * R))[None, :], ny, 0)
     zero = np.zeros((ny, nx))
     return Workload("sod_tube", rho, zero.copy(), zero.copy(), T, 2.0, 2.0 * ny / nx)
+
+
+def acoustic_wave(n: int = 256, ny: int = 4, amp: float = 1e-3, theta: float = 1.0, mach: float = 0.0,
+                  gamma: float = 1.4, R: float = 1.0) -> Workload:
+    """Adiabatic standing sound wave on a periodic unit line (pseudo-1-D):
+    rho = 1 + amp cos(2 pi x), T = theta (1 + (gamma - 1) amp cos(2 pi x)),
+    on a uniform flow u_x = mach sqrt(gamma R theta)."""
+    x = _centres(n, 1.0)
+    c = np.cos(2 * np.pi * x)
+    rho = np.repeat((1.0 + amp * c)[None, :], ny, 0)
+    T = np.repeat((theta * (1.0 + (gamma - 1.0) * amp * c))[None, :], ny, 0)
+    ux = np.full((ny, n), mach * np.sqrt(gamma * R * theta))
+    return Workload("acoustic_wave", rho, ux, np.zeros((ny, n)), T, 1.0, ny / n,
+                    {"theta": theta, "mach": mach, "amp": amp})

@@ -560,3 +560,37 @@ def riemann_density(x, t, left, right, gamma):
                 else:
                     out[k] = rr * (2 / (gamma + 1) - (gamma - 1) / ((gamma + 1) * cr) * (ur - s)) ** (2 / (gamma - 1))
     return out
+
+
+# ---------------------------------------------------------------- dispersion: speed of sound (Sec. IV)
+@pytest.mark.parametrize("split", (1, 2))
+@pytest.mark.parametrize("theta,mach", ((0.8, 0.0), (1.0, 0.0), (1.25, 0.0), (1.0, 0.5), (1.0, 1.0)))
+def test_speed_of_sound(split, theta, mach):
+    """Speed of sound from an adiabatic standing wave (amplitude 1e-3, 256
+    cells, FP64): the zero crossings of the density mode, with the advective
+    phase of the flow removed, against sqrt(gamma R T) at T = theta T_ref,
+    on flows up to Mach 1."""
+    from synth import acoustic_wave
+    n = 256
+    wl = acoustic_wave(n, 4, theta=theta, mach=mach)
+    s, p = solver(wl, split=split, storage="f64", Pr=0.71, tau_ref=1e-3, cfl=0.2)
+    dt = s.dt
+    c0 = math.sqrt(1.4 * theta)
+    U = mach * c0
+    e = np.exp(-2j * math.pi * (np.arange(n) + 0.5) / n)
+    times, vals = [], []
+    chunk = 10
+    for m in range(int(1.3 / (c0 * dt)) // chunk):
+        a = 2 * (s.moments(fields=True, sums=False)["rho"].cpu().numpy()[0] * e).mean()
+        t = m * chunk * dt
+        times.append(t)
+        vals.append((a * np.exp(2j * math.pi * U * t)).real)
+        s.step(chunk)
+    s.close()
+    v = np.array(vals)
+    tt = np.array(times)
+    z = [tt[i] - v[i] * (tt[i + 1] - tt[i]) / (v[i + 1] - v[i]) for i in range(len(v) - 1) if v[i] * v[i + 1] < 0]
+    assert len(z) >= 2
+    c = 0.5 / np.diff(z).mean()
+    print(f"[sound] split {split} theta {theta} Ma {mach}: c / sqrt(gamma R T) - 1 = {c / c0 - 1:.2e}", flush=True)
+    assert abs(c / c0 - 1) < 1e-3  # measured 0.8e-4 to 2.8e-4
