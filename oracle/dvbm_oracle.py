@@ -48,6 +48,12 @@ design notes):
   interior rows, ghost ``k`` (k = 1, 2 away from the wall) taking the fields
   ``rho_G = rho_B, u_G = 2 u_W - u_B, T_G = 2 T_W - T_B`` of interior row
   ``k`` and the populations ``X^eq(G) + (X_B - X^eq(B))``.
+* Split II with ``Pr > 1``: the QE pressure tensor of f* is taken as printed
+  in the discrete form (Sec. II D), with the trace of ``P_f - P_eq`` removed
+  for energy conservation.  The trace then relaxes in the first stage, so the
+  bulk viscosity follows ``tau_1`` (the thermal time), not the ``tau_2`` that
+  the Chapman-Enskog result (Eq. visc_bluk_2) names.  Split I keeps the trace
+  in f* and follows ``tau_2``.  The sound-attenuation pins measure this.
 """
 
 from __future__ import annotations

@@ -18,6 +18,7 @@ import torch
 
 from oracle import dvbm_oracle as O
 from paper_2510_04197_amd import DVBMError, Solver, dvbm, make_params
+from closed_forms import sound_decay_rate
 from synth import isentropic_vortex, shear_wave, shock_vortex, smooth_random, sod_tube, thermal_wave, uniform
 
 pytestmark = pytest.mark.gpu
@@ -632,3 +633,44 @@ def test_thermal_diffusivity_on_a_flow(split, Pr, mach):
     print(f"[thermal] split {split} Pr {Pr} Ma {mach}: alpha / (nu/Pr - U^2 dt/2) - 1 = {alpha / expected - 1:.2e}"
           f" (forward-Euler term {0.5 * U * U * dt * Pr / mu:.1e} of nu/Pr)", flush=True)
     assert abs(alpha - expected) < 0.01 * mu / Pr  # measured 5e-5 to 1.3e-3; 7.9e-3 for split II, Pr 0.5, Mach 1
+
+
+# ---------------------------------------------------------------- dissipation: sound attenuation and bulk viscosity (Sec. II C, IV)
+@pytest.mark.parametrize("split", (1, 2))
+@pytest.mark.parametrize("Pr", (0.5, 2.0))
+@pytest.mark.parametrize("gamma,mach", ((1.4, 0.0), (5.0 / 3.0, 0.0), (4.0 / 3.0, 0.0), (1.4, 0.5)))
+def test_sound_attenuation(split, Pr, gamma, mach):
+    """Decay of an adiabatic standing sound wave (amplitude 1e-3, 256 cells,
+    FP64, mu = 2e-3, half a decay time): the right- and left-running waves
+    u_k +- p_k / (rho c) (which the entropy mode, carrying no pressure, does
+    not enter) each decay as exp(-Gamma k^2 t), less the anti-diffusion
+    (U +- c)^2 dt / 2 that forward Euler adds to a wave of that speed."""
+    from synth import acoustic_wave
+    n, mu = 256, 2e-3
+    wl = acoustic_wave(n, 4, gamma=gamma, mach=mach)
+    s, p = solver(wl, split=split, storage="f64", Pr=Pr, tau_ref=mu, gamma=gamma, cfl=0.2)
+    dt = s.dt
+    c = math.sqrt(gamma)
+    U = mach * c
+    k = 2 * math.pi
+    G = sound_decay_rate(split, Pr, gamma, mu)
+    e = np.exp(-1j * k * (np.arange(n) + 0.5) / n)
+    nsteps = int(0.5 / (G * k * k) / dt)
+    chunk = max(1, nsteps // 100)
+    ts, lr, ll = [], [], []
+    for m in range(nsteps // chunk):
+        mo = {q: v.cpu().numpy()[0] for q, v in s.moments(fields=True, sums=False).items()}
+        uk = 2 * (mo["ux"] * e).mean()
+        pk = 2 * (mo["rho"] * mo["T"] * e).mean()
+        ts.append(m * chunk * dt)
+        lr.append(math.log(abs(uk + pk / c)))
+        ll.append(math.log(abs(uk - pk / c)))
+        s.step(chunk)
+    s.close()
+    worst = 0.0
+    for logs, a in ((lr, U + c), (ll, U - c)):
+        g = -np.polyfit(np.array(ts), np.array(logs), 1)[0] / (k * k)
+        worst = max(worst, abs(g - (G - 0.5 * a * a * dt)) / G)
+    print(f"[bulk] split {split} Pr {Pr} gamma {gamma:.3f} Ma {mach}: |Gamma_measured - Gamma| / Gamma = {worst:.2e}"
+          f" (forward-Euler term {0.5 * (U + c) ** 2 * dt / G:.2f} of Gamma)", flush=True)
+    assert worst < 1e-2  # measured 1.4e-5 to 8.7e-4; 4.7e-3 for split I, Pr 0.5, Mach 0.5
