@@ -152,18 +152,20 @@ def rankine_hugoniot(rho_l: float, p_l: float, mach_s: float, gamma: float):
 
 def shock_vortex(nx: int = 2048, ny: int = 1024, mach_s: float = 1.2, mach_v: float = 0.25,
                  r_frac: float = 0.075, gamma: float = 1.4, R: float = 1.0, Re_v: float = 800.0,
-                 Lx: float = 2.0, Ly: float = 1.0) -> Workload:
+                 Lx: float = 2.0, Ly: float = 1.0, x_shock: float | None = None) -> Workload:
     """Stationary normal shock hit by an isentropic vortex (Sec. III F).
 
-    Pre-shock ``rho = p = 1`` for ``x < Lx/2``, Rankine-Hugoniot post-shock
-    state beyond. The vortex of radius ``r_frac Ly`` sits upstream at
-    ``(Lx/2 - 2 r_v, Ly/2)`` (the paper's spacing of two radii between the
-    vortex centre and the shock) and perturbs both sides. The dynamic
-    viscosity follows from ``Re_v = rho_l c_l r_v / mu``.
+    Pre-shock ``rho = p = 1`` for ``x < x_shock`` (default ``Lx/2``),
+    Rankine-Hugoniot post-shock state beyond. The vortex of radius
+    ``r_frac Ly`` sits upstream at ``(x_shock - 2 r_v, Ly/2)`` (the paper's
+    spacing of two radii between the vortex centre and the shock) and
+    perturbs both sides. The dynamic viscosity follows from
+    ``Re_v = rho_l c_l r_v / mu``. The paper's case C is
+    ``shock_vortex(1680, 1440, 1.2, 0.25, 1/24, Lx=28, Ly=24, x_shock=8)``.
     """
     (rho_l, p_l, u_l), (rho_r, p_r, u_r) = rankine_hugoniot(1.0, 1.0, mach_s, gamma)
     X, Y = _grid(nx, ny, Lx, Ly)
-    xs = 0.5 * Lx
+    xs = 0.5 * Lx if x_shock is None else float(x_shock)
     left = X < xs
     rho_inf = np.where(left, rho_l, rho_r)
     p_inf = np.where(left, p_l, p_r)
@@ -181,7 +183,8 @@ def shock_vortex(nx: int = 2048, ny: int = 1024, mach_s: float = 1.2, mach_v: fl
     T = p / (rho * R)
     mu = rho_l * c_l * rv / Re_v
     return Workload("shock_vortex", rho, ux, uy, T, Lx, Ly,
-                    {"gamma": gamma, "R": R, "mu": mu, "rv": rv, "p_post": p_r,
+                    {"gamma": gamma, "R": R, "mu": mu, "rv": rv, "p_post": p_r, "c_l": float(c_l),
+                     "T_post": p_r / (rho_r * R), "u_post": u_r, "centre": (xv, yv),
                      "mach_s": mach_s, "mach_v": mach_v})
 
 

@@ -674,3 +674,86 @@ def test_sound_attenuation(split, Pr, gamma, mach):
     print(f"[bulk] split {split} Pr {Pr} gamma {gamma:.3f} Ma {mach}: |Gamma_measured - Gamma| / Gamma = {worst:.2e}"
           f" (forward-Euler term {0.5 * (U + c) ** 2 * dt / G:.2f} of Gamma)", flush=True)
     assert worst < 1e-2  # measured 1.4e-5 to 8.7e-4; 4.7e-3 for split I, Pr 0.5, Mach 0.5
+
+
+# ---------------------------------------------------------------- shock-vortex sound diagnostics (Sec. IV)
+def test_shock_vortex_case_c_sound():
+    """Case C of the shock-vortex interaction (Ma_s 1.2, Ma_v 0.25, Re_v 800,
+    Pr 0.75, split II) on the 28 x 24 r_v domain at 60 cells per r_v, shock at
+    x = 8, vortex at (6, 12), zero-gradient x boundaries; CFL 0.1 (at CFL 0.2
+    the post-shock dt / tau_1 is 1.2 and the run diverges).  Properties that
+    hold without the reference DNS data:
+    * the vortex centre (its vorticity minimum: it turns clockwise) moves with
+      the post-shock flow speed u_r (t* 4 to 10);
+    * along the 45 degree ray, the peaks of the precursor and of the second
+      sound move outwards at the post-shock sound speed, approached from above
+      as the fronts grow (a front centred off the vortex centre runs ahead of
+      c_r along the ray by a share that falls as its radius grows): between
+      t* = 8 and 10 within 0 to 5 % above c_r / c_l per unit t*, and slower
+      than between t* = 6 and 8 (measured 3.5 % and 0.8 % above);
+    * ahead of the precursor (r from 9 to 13 r_v at t* = 6) the field is quiet;
+    * float32 and float64 storage give the same vortex centre and sound
+      pressure at t* = 6 (8,800 steps), within what 8,800 float32 steps
+      through a shock accumulate: relative L2 of the pressure 1.3e-4, largest
+      at the shock (a sub-cell shift of it), and 1.2e-4 of p_r along the
+      ray (2 % of the precursor's peak)."""
+    from paper_2510_04197_amd import diagnostics as Dg
+    from synth import shock_vortex
+    wl = shock_vortex(1680, 1440, 1.2, 0.25, 1.0 / 24.0, Lx=28.0, Ly=24.0, x_shock=8.0)
+    ph = wl.phys
+    c_ratio = math.sqrt(ph["T_post"])  # c_r / c_l with T_l = 1
+    radii = np.arange(0.0, 13.0, 0.05)
+    rays, centres, fields6 = {}, {}, {}
+    for storage, t_stars in (("f32", (4.0, 6.0, 8.0, 10.0)), ("f64", (6.0,))):
+        print(f"[shock-vortex] case C, {storage}", flush=True)
+        s, p = solver(wl, split=2, storage=storage, Pr=0.75, gamma=1.4, tau_ref=ph["mu"], bc_x="zero_gradient",
+                      bc_y="periodic", cfl=0.1)
+        dt, n, c = s.dt, 0, ph["centre"]
+        for ts in t_stars:
+            target = int(round(ts * ph["rv"] / ph["c_l"] / dt))
+            guess = (c[0] + (target - n) * dt * ph["u_post"], c[1])
+            s.step(target - n)
+            n = target
+            m = {k: v.cpu().numpy() for k, v in s.moments(fields=True, sums=False).items()}
+            ps = Dg.sound_pressure(m["rho"], m["T"], ph["p_post"])
+            assert np.isfinite(ps).all()
+            c = Dg.vortex_centre(Dg.vorticity(m["ux"], m["uy"], wl.dx, wl.dy), wl.dx, wl.dy, guess, 1.5)
+            centres[storage, ts] = (n * dt, c)
+            rays[storage, ts] = Dg.ray(ps, c, 45.0, radii, wl.dx, wl.dy)
+            if ts == 6.0:
+                fields6[storage] = ps
+        s.close()
+
+    (t4, c4), (t10, c10) = centres["f32", 4.0], centres["f32", 10.0]
+    speed = (c10[0] - c4[0]) / (t10 - t4)
+    print(f"[shock-vortex] vortex speed / u_r - 1 = {speed / ph['u_post'] - 1:.2e}", flush=True)
+    assert abs(speed / ph["u_post"] - 1) < 5e-3
+
+    def peak(pr, lo, hi, sign):
+        idx = np.where((radii >= lo) & (radii <= hi))[0]
+        k = idx[np.argmax(sign * pr[idx])]
+        a, b, cc = pr[k - 1], pr[k], pr[k + 1]
+        return radii[k] + 0.05 * 0.5 * (a - cc) / (a - 2 * b + cc)
+
+    for name, lo, hi, sign in (("precursor", 4.5, 12.5, 1), ("second sound", 2.5, 9.5, -1)):
+        r6, r8, r10 = (peak(rays["f32", ts], lo, hi, sign) for ts in (6.0, 8.0, 10.0))
+        early, late = (r8 - r6) / 2 / c_ratio, (r10 - r8) / 2 / c_ratio
+        print(f"[shock-vortex] {name} at r/r_v {r6:.3f} {r8:.3f} {r10:.3f}; speed / c_r: {early:.4f} then {late:.4f}",
+              flush=True)
+        assert 1.0 <= late < 1.05 and late < early
+
+    pr6 = rays["f32", 6.0]
+    front = peak(pr6, 4.5, 12.5, 1)
+    ahead = np.abs(pr6[radii >= 9.0]).max()
+    print(f"[shock-vortex] t* 6: precursor {pr6.max():.2e} at {front:.2f}; max |p_sound| ahead {ahead:.1e}", flush=True)
+    assert front < 7.5 and ahead < 0.1 * pr6.max()
+
+    c64 = centres["f64", 6.0][1]
+    shift = math.hypot(c64[0] - centres["f32", 6.0][1][0], c64[1] - centres["f32", 6.0][1][1])
+    ray_diff = np.abs(Dg.ray(fields6["f32"], c64, 45.0, radii, wl.dx, wl.dy) - rays["f64", 6.0])
+    p32, p64 = fields6["f32"] + 1.0, fields6["f64"] + 1.0
+    rel_l2 = float(np.linalg.norm(p32 - p64) / np.linalg.norm(p64))
+    print(f"[shock-vortex] f32 vs f64 at t* 6: centre shift {shift:.1e} r_v; along the ray (same centre) max "
+          f"{ray_diff.max():.1e}, beyond r = 1: {ray_diff[radii >= 1.0].max():.1e}; pressure rel. L2 {rel_l2:.1e}; "
+          f"max |dp/p_r| {np.abs(p32 - p64).max():.1e}", flush=True)
+    assert shift < 2e-3 and rel_l2 < 3e-4 and ray_diff.max() < 3e-4  # measured 7.4e-4, 1.3e-4, 1.2e-4
