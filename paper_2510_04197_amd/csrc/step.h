@@ -152,12 +152,15 @@ __device__ inline void cell_update(const typename S::T* __restrict__ src, typena
   R bf[5][5], bg[3][3], om1;
   collision_coeffs<SPLIT, PRM, R>(m, kp, kp.om_scale, kp.Pr, bf, bg, om1);
 
-  // collision: (1 - om1) X + expansion of b
+  // collision: (1 - om1) X + expansion of b.  For 32/64-bit storage X holds
+  // the increment -om1 X + expansion, added to the stored value once at the
+  // end (one rounding at the magnitude of X)
   const R keep = R(1) - om1;
+  const R scale = S::dev ? keep : -om1;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    X[0][i] *= keep;
-    X[1][i] *= keep;
+    X[0][i] *= scale;
+    X[1][i] *= scale;
   }
   expand_add<N1, Set<SPLIT>::NF>(bf, X[0]);
   expand_add<N1, 2>(bg, X[1]);
@@ -199,7 +202,7 @@ __device__ inline void cell_update(const typename S::T* __restrict__ src, typena
         div += ky * R(xb) * dface_neg(ly(oym1, -1), c0, ly(oyp1, 1), ly(oyp2, 2), beta2);
       const double w = weight<SPLIT>(i);
       const R rr = S::dev ? R(d == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i)) : R(0);
-      const R xnew = X[d][i] - (S::dev ? R(w) * div : div);
+      const R xnew = S::dev ? X[d][i] - R(w) * div : c0 + (X[d][i] - div);
       Buf<T>::st(rsrc_dst[d], so, o0, S::enc(xnew, R(1.0 / w), rr));
     }
   }
@@ -378,8 +381,9 @@ __device__ inline void tile_update(const typename S::T* __restrict__ src, typena
       const uint32_t so = i * plane_bytes;
       const R rr = S::dev ? R(d == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i)) : R(0);
       const R X = S::dev ? R(w) * (rr + c0) : c0;
-      // collision: (1 - om1) X + w_i sum_p He_p(xi_a)/p! c_p
-      R xn = keep * X;
+      // collision: (1 - om1) X + w_i sum_p He_p(xi_a)/p! c_p; for 32/64-bit
+      // storage the increment is summed first and added to X once
+      R xn = S::dev ? keep * X : -om1 * X;
 #pragma unroll
       for (int p = 0; p <= NMAX; ++p) {
         if (p > N) continue;
@@ -396,7 +400,10 @@ __device__ inline void tile_update(const typename S::T* __restrict__ src, typena
         div += ky * R(xb) * dface_pos(buf[me - 2 * W], buf[me - W], c0, buf[me + W], beta2);
       else if (xb < 0.0)
         div += ky * R(xb) * dface_neg(buf[me - W], c0, buf[me + W], buf[me + 2 * W], beta2);
-      xn -= S::dev ? R(w) * div : div;
+      if constexpr (S::dev)
+        xn -= R(w) * div;
+      else
+        xn = X + (xn - div);
       if (valid) Buf<T>::st(rsrc_dst[d], so, o0, S::enc(xn, R(1.0 / w), rr));
     });
   });

@@ -384,7 +384,10 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
             if (h != 0.0) xn += R(h) * c[p];
           }
         } else {
-          xn = keep * c0;
+          // the small increments are summed first and added to X once: the
+          // step changes X by tens of ulps, so every rounding at X's magnitude
+          // would be a sizeable share of it
+          xn = -om1 * c0;
 #pragma unroll
           for (int p = 0; p <= 4; ++p) {
             if (p > N) continue;
@@ -408,7 +411,11 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
           div += ky * R(xb) * (fa - fbelow[i]);
           fbelow[i] = fa;
         }
-        xn -= div;  // stored values and deviations share the flux form (L is homogeneous)
+        // stored values and deviations share the flux form (L is homogeneous)
+        if constexpr (S::dev)
+          xn -= div;
+        else
+          xn = c0 + (xn - div);
         if constexpr (S::dev)
           Buf<T>::st(rsrc_dst, uint32_t(i) * plane_bytes + r_st, vo_st, S::enc_dev(xn));
         else if constexpr (sizeof(T) == 8)
