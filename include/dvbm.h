@@ -31,8 +31,8 @@
  *    weight w_a w_b, with the 1-D Gauss-Hermite nodes xi ascending
  *    (q1 = 4 for split I, Q = 16; q1 = 5 for split II, Q = 25).
  *  - Storage DVBM_F64 / DVBM_F32 stores X itself.  DVBM_BF16_DEV /
- *    DVBM_FP16_DEV store the deviation (X_i - X_ref_i) / w_i rounded to
- *    nearest-even, where X_ref is the rest equilibrium (rho = 1, u = 0,
+ *    DVBM_FP16_DEV / DVBM_F32_DEV store the deviation (X_i - X_ref_i) / w_i
+ *    rounded to nearest-even, where X_ref is the rest equilibrium (rho = 1, u = 0,
  *    T = T_ref): f_ref_i = w_i; g_ref_i = w_i (Cv - R) T_ref (split II) or
  *    w_i (Cv T_ref + R T_ref (|xi_i|^2 - 2) / 2) (split I).  F64 computes in
  *    float64; the other formats compute in float32 with float64 per-node
@@ -59,7 +59,11 @@ extern "C" {
 #define DVBM_ENAN (-3)   /* non-finite or non-physical state (rho <= 0, T <= 0) */
 #define DVBM_ESTIFF (-4) /* dt / tau_1 > 2 for the initial state */
 
-enum dvbm_storage { DVBM_F64 = 0, DVBM_F32 = 1, DVBM_BF16_DEV = 2, DVBM_FP16_DEV = 3 };
+/* DVBM_F32_DEV keeps float32's bytes but stores the deviation: near the rest
+ * state its values are small, so a rounding of the stored value is that much
+ * finer than one of X itself.  The column-sweep kernel also does its
+ * arithmetic in deviation units; the adjoint does not take this format. */
+enum dvbm_storage { DVBM_F64 = 0, DVBM_F32 = 1, DVBM_BF16_DEV = 2, DVBM_FP16_DEV = 3, DVBM_F32_DEV = 4 };
 /* Boundaries: periodic; zero-gradient (two ghost layers copy the nearest
  * interior cell); DVBM_WALL (bc_y only): no-slip walls on the faces below row
  * 0 and above row ny-1 with temperatures wall_T and x velocities wall_ux

@@ -27,8 +27,8 @@ HIPCC_FLAGS = [
 # csrc/dvbm.hip is compiled once as the main unit (C ABI, small kernels) and
 # once per split x storage as a kernel unit holding that pair's step and
 # adjoint kernels, so that the units compile in parallel.
-STORES = ("dvbm::StoreF64", "dvbm::StoreF32", "dvbm::StoreBF16", "dvbm::StoreF16")
-PARTS = [(4 * (split - 1) + k + 1, STORES[k]) for split in (1, 2) for k in range(4)]
+STORES = ("dvbm::StoreF64", "dvbm::StoreF32", "dvbm::StoreBF16", "dvbm::StoreF16", "dvbm::StoreF32Dev")
+PARTS = [(len(STORES) * (split - 1) + k + 1, STORES[k]) for split in (1, 2) for k in range(len(STORES))]
 
 
 def hipcc() -> str:

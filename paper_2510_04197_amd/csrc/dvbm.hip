@@ -536,13 +536,13 @@ int hip_fail(hipError_t e, const char* what) {
     if (_e != hipSuccess) return hip_fail(_e, #expr);   \
   } while (0)
 
-int storage_bytes(int s) { return s == DVBM_F64 ? 8 : s == DVBM_F32 ? 4 : 2; }
+int storage_bytes(int s) { return s == DVBM_F64 ? 8 : (s == DVBM_F32 || s == DVBM_F32_DEV) ? 4 : 2; }
 
 std::string check_params(const dvbm_params* p) {
   if (!p) return "params is NULL";
   if (p->nx < 4 || p->ny < 4) return "nx and ny must be >= 4";
   if (p->split != 1 && p->split != 2) return "split must be 1 or 2";
-  if (p->storage < DVBM_F64 || p->storage > DVBM_FP16_DEV) return "unknown storage";
+  if (p->storage < DVBM_F64 || p->storage > DVBM_F32_DEV) return "unknown storage";
   if ((p->bc_x != DVBM_PERIODIC && p->bc_x != DVBM_ZERO_GRADIENT) ||
       (p->bc_y != DVBM_PERIODIC && p->bc_y != DVBM_ZERO_GRADIENT && p->bc_y != DVBM_WALL))
     return "unknown boundary condition (walls are supported in y only)";
@@ -789,12 +789,12 @@ void adjoint_bc(const dvbm_handle* h, const void* state, const LT* lam1, LT* lam
 }  // namespace dvbm_launch
 
 #if defined(DVBM_PART)
-// kernel unit DVBM_PART = 4 (split - 1) + storage + 1
-template void dvbm_launch::step<(DVBM_PART - 1) / 4 + 1, DVBM_PART_STORE>(const dvbm_handle*, const void*, void*);
-#if (DVBM_PART - 1) % 4 < 2
-template void dvbm_launch::adjoint<(DVBM_PART - 1) / 4 + 1, DVBM_PART_STORE, double>(
+// kernel unit DVBM_PART = 5 (split - 1) + storage + 1
+template void dvbm_launch::step<(DVBM_PART - 1) / 5 + 1, DVBM_PART_STORE>(const dvbm_handle*, const void*, void*);
+#if (DVBM_PART - 1) % 5 < 2
+template void dvbm_launch::adjoint<(DVBM_PART - 1) / 5 + 1, DVBM_PART_STORE, double>(
     const dvbm_handle*, const void*, const double*, double*, double*, double*);
-template void dvbm_launch::adjoint<(DVBM_PART - 1) / 4 + 1, DVBM_PART_STORE, float>(
+template void dvbm_launch::adjoint<(DVBM_PART - 1) / 5 + 1, DVBM_PART_STORE, float>(
     const dvbm_handle*, const void*, const float*, float*, double*, double*);
 #endif
 #else
@@ -809,10 +809,12 @@ DVBM_EXTERN_STEP(1, StoreF64)
 DVBM_EXTERN_STEP(1, StoreF32)
 DVBM_EXTERN_STEP(1, StoreBF16)
 DVBM_EXTERN_STEP(1, StoreF16)
+DVBM_EXTERN_STEP(1, StoreF32Dev)
 DVBM_EXTERN_STEP(2, StoreF64)
 DVBM_EXTERN_STEP(2, StoreF32)
 DVBM_EXTERN_STEP(2, StoreBF16)
 DVBM_EXTERN_STEP(2, StoreF16)
+DVBM_EXTERN_STEP(2, StoreF32Dev)
 DVBM_EXTERN_ADJ(1, StoreF64)
 DVBM_EXTERN_ADJ(1, StoreF32)
 DVBM_EXTERN_ADJ(2, StoreF64)
@@ -828,6 +830,7 @@ void dispatch(const dvbm_params& p, A&&... args) {
       case DVBM_F64: F<2, StoreF64>::run(args...); break;
       case DVBM_F32: F<2, StoreF32>::run(args...); break;
       case DVBM_BF16_DEV: F<2, StoreBF16>::run(args...); break;
+      case DVBM_F32_DEV: F<2, StoreF32Dev>::run(args...); break;
       default: F<2, StoreF16>::run(args...); break;
     }
   } else {
@@ -835,6 +838,7 @@ void dispatch(const dvbm_params& p, A&&... args) {
       case DVBM_F64: F<1, StoreF64>::run(args...); break;
       case DVBM_F32: F<1, StoreF32>::run(args...); break;
       case DVBM_BF16_DEV: F<1, StoreBF16>::run(args...); break;
+      case DVBM_F32_DEV: F<1, StoreF32Dev>::run(args...); break;
       default: F<1, StoreF16>::run(args...); break;
     }
   }

@@ -82,6 +82,17 @@ struct StoreF16 {
   __device__ static T enc_dev(C d) { return T(d); }  // a deviation already in units of w
 };
 
+// float32 deviation (X - X_ref) / w: float32's bytes, with the roundings of
+// a value of the deviation's size rather than of X's.
+struct StoreF32Dev {
+  using T = float;
+  using C = float;
+  static constexpr bool dev = true;
+  __device__ static C raw(T v) { return v; }
+  __device__ static T enc(C x, C winv, C r) { return x * winv - r; }
+  __device__ static T enc_dev(C d) { return d; }  // a deviation already in units of w
+};
+
 // ------------------------------------------------------------ small helpers
 __device__ inline double med3(double a, double b, double c) { return fmax(fmin(a, b), fmin(fmax(a, b), c)); }
 __device__ inline float med3(float a, float b, float c) { return __builtin_amdgcn_fmed3f(a, b, c); }

@@ -23,7 +23,7 @@ DVBM_EHIP = -2
 DVBM_ENAN = -3
 DVBM_ESTIFF = -4
 
-STORAGE = {"f64": 0, "f32": 1, "bf16_dev": 2, "fp16_dev": 3}
+STORAGE = {"f64": 0, "f32": 1, "bf16_dev": 2, "fp16_dev": 3, "f32_dev": 4}
 BC = {"periodic": 0, "zero_gradient": 1, "wall": 2}
 VISC = {"const_mu": 0, "const_tau": 1}
 KERNEL = {"auto": 0, "cell": 1, "sweep": 2, "tile": 3}

@@ -92,9 +92,12 @@ def test_null_handle_calls_fail_cleanly():
 def test_sweep_kernel_distribution_limit():
     from paper_2510_04197_amd import dvbm
     lib = dvbm.load_library()
-    for storage in ("f64", "f32", "bf16_dev", "fp16_dev"):
+    for storage in ("f64", "f32", "bf16_dev", "fp16_dev", "f32_dev"):
         p = dvbm.make_params(16, 16, storage=storage, kernel="sweep")
         assert lib.dvbm_buffer_bytes(ctypes.byref(p)) > 0, storage
+    # float32 deviations take float32's bytes
+    sizes = [lib.dvbm_buffer_bytes(ctypes.byref(dvbm.make_params(100, 30, storage=st))) for st in ("f32", "f32_dev")]
+    assert sizes[0] == sizes[1]
     # a float32 distribution above 2 GiB: 25 planes x 5120 x 4224 cells x 4 B
     p = dvbm.make_params(5120, 4224, storage="f32", kernel="sweep")
     assert lib.dvbm_buffer_bytes(ctypes.byref(p)) == 0
