@@ -259,6 +259,34 @@ def precision_errors(fields, ref):
     return out
 
 
+def vortex_precision(device, nsteps=5000):
+    """The 1024^2 Mach-1 isentropic vortex over its 5000 steps: relative L2 of
+    rho and T of each float32 storage against the float64-storage run, on the
+    full grid and on the 128^2 grid of 8 x 8 block averages."""
+    import torch
+
+    from paper_2510_04197_amd import Solver, make_params
+
+    wl, phys = workload_fields("vortex_1024")
+    fields = {}
+    for st in ("f64", "f32", "f32_dev"):
+        s = Solver(make_params(wl.nx, wl.ny, dx=wl.dx, dy=wl.dy, storage=st, **phys), wl.rho, wl.ux, wl.uy, wl.T,
+                   device=device)
+        s.step(nsteps)
+        m = s.moments(fields=True, sums=False)
+        fields[st] = {k: m[k] for k in ("rho", "T")}
+        s.close()
+    pool = torch.nn.functional.avg_pool2d
+    out = {"workload": "vortex_1024", "steps": nsteps, "reference": "float64-storage GPU run"}
+    for st in ("f32", "f32_dev"):
+        for k in ("rho", "T"):
+            a, b = fields[st][k], fields["f64"][k]
+            out.setdefault(st, {})[f"rel_L2_{k}"] = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+            a8, b8 = pool(a[None, None], 8), pool(b[None, None], 8)
+            out[st][f"rel_L2_{k}_128"] = float(torch.linalg.vector_norm(a8 - b8) / torch.linalg.vector_norm(b8))
+    return out
+
+
 def adjoint_cost(device, n=256, nsteps=200, storage="f32", Ks=(10, 50)):
     """Gradient of L = sum (T(200 steps) - T_target)^2 w.r.t. T0, tau_ref, Pr on the 256^2 periodic
     Gaussian-bump workload: time of forward + checkpointed recomputation + reverse sweep, divided by
@@ -419,6 +447,10 @@ def main():
             if st != "f64":
                 precision[st] = precision_errors(fl, fields["f64"])
     del fields, main_fields
+    vortex = None
+    if precision is not None:
+        print("[bench] float32 precision on the 1024x1024 vortex, 5000 steps", file=sys.stderr, flush=True)
+        vortex = vortex_precision(device)
     adjoint = None
     if not args.no_adjoint:
         print("[bench] adjoint cost on the 256x256 gradient workload", file=sys.stderr, flush=True)
@@ -457,6 +489,7 @@ def main():
         "modes": {k: {kk: (float("%.5g" % vv) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                   for k, v in modes.items()},
         "precision": precision,
+        "precision_vortex": vortex,
         "adjoint": adjoint,
     }
     print(json.dumps(line), flush=True)
