@@ -331,7 +331,7 @@ def test_largest_grid_fp64_sampled():
 @pytest.mark.parametrize("split", (1, 2))
 @pytest.mark.parametrize("Pr", (0.5, 1.0, 2.0))
 @pytest.mark.parametrize("bc_x", ("periodic", "zero_gradient"))
-@pytest.mark.parametrize("storage,tol", (("f64", 1e-12), ("f32", 1e-5)))
+@pytest.mark.parametrize("storage,tol", (("f64", 1e-12), ("f32", 1e-5), ("f32_dev", 1e-5)))
 def test_walls_match_oracle(split, Pr, bc_x, storage, tol):
     """Walls in y at temperatures 0.95 and 1.1, the upper one moving at 0.3:
     an off-equilibrium start on 11 x 9 cells (a ragged tile in both
@@ -463,7 +463,7 @@ def test_stiff_relaxation_rejected():
     assert e.value.code == dvbm.DVBM_ESTIFF
 
 
-@pytest.mark.parametrize("storage", ("f64", "f32", "bf16_dev"))
+@pytest.mark.parametrize("storage", ("f64", "f32", "bf16_dev", "f32_dev"))
 def test_step_from_matches_step(storage):
     """dvbm_step_from(src, dst) computes the same step as dvbm_step and leaves the handle's state alone."""
     wl = smooth_random(70, 37, seed=12)
@@ -476,7 +476,7 @@ def test_step_from_matches_step(storage):
     assert s.state_index == idx and torch.equal(s.state_buffer, src)
     s.step(1)
     # compare the cells only (the pitch padding of the two buffers holds unrelated bytes)
-    dt = {"f64": torch.float64, "f32": torch.float32, "bf16_dev": torch.int16}[storage]
+    dt = {"f64": torch.float64, "f32": torch.float32, "bf16_dev": torch.int16, "f32_dev": torch.float32}[storage]
     pitch = dvbm.load_library().dvbm_pitch(ctypes.byref(p))
 
     def cells(buf):
