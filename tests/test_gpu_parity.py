@@ -349,21 +349,27 @@ def test_walls_match_oracle(split, Pr, bc_x, storage, tol):
         assert rel(f - f0, fo - f0) < 1e-9 and rel(g - g0, go - g0) < 1e-9
 
 
+@pytest.mark.parametrize("Ma,Ec", ((0.5, 4.0), (1.2, 40.0)))
 @pytest.mark.parametrize("split", (2, 1))
 @pytest.mark.parametrize("Pr", (0.5, 1.0, 2.0))
-def test_thermal_couette_steady_profile(split, Pr):
-    """Thermal Couette flow at the paper's parameters (Sec. IV: Ma = 0.5,
-    Ec = 4, Re = 100, T_C = T_ref, linear initial profiles), 128 rows as in
-    the paper, CFL 0.2 (the fastest lattice velocity, 2.86 sqrt(R T_ref),
-    sets the stable step: CFL 0.5 diverges), run for about 8 slowest-mode
-    decay times: the temperature against
-    (T - T_C)/(T_H - T_C) = y + Pr Ec/2 y (1 - y).  Measured: 0.24-0.47 % of
-    the profile's peak, split I at Pr = 2 1.9 %.  The error does not fall
-    below ~0.4 % with resolution (split II, Pr = 1: 32 rows 1.1 %, 64 rows
-    0.36 %, 256 rows 0.40 %); split I converges more slowly (Pr = 1: 64 rows
-    0.97 %, 128 rows 0.37 %)."""
+def test_thermal_couette_steady_profile(split, Pr, Ma, Ec):
+    """Thermal Couette flow at the paper's two parameter sets (Sec. IV:
+    Ma = 0.5, Ec = 4 and Ma = 1.2, Ec = 40; Re = 100, T_C = T_ref, linear
+    initial profiles), 128 rows as in the paper, CFL 0.2 (the fastest lattice
+    velocity, 2.86 sqrt(R T_ref), sets the stable step: CFL 0.5 diverges),
+    run for about 8 slowest-mode decay times: the temperature against
+    (T - T_C)/(T_H - T_C) = y + Pr Ec/2 y (1 - y), exact for constant mu and
+    kappa whatever the density.  Measured at Ma = 0.5: 0.24-0.41 % of the
+    profile's peak, split I at Pr = 2 1.9 %; the error does not fall below
+    ~0.4 % with resolution (split II, Pr = 1: 32 rows 1.1 %, 64 rows 0.36 %,
+    256 rows 0.40 %); split I converges more slowly (Pr = 1: 64 rows 0.97 %,
+    128 rows 0.37 %).  At Ma = 1.2, Ec = 40, where viscous heating makes the
+    profile ten times the wall difference: 1.0-3.5 %, first order in the row
+    spacing and independent of the time step (split II, Pr = 1: 64 / 128 /
+    256 rows 5.5 / 2.6 / 1.1 %, the same at CFL 0.1; the wall velocity's slip
+    halves likewise, 0.85 / 0.43 / 0.21 % of u_0)."""
     import math
-    ny, nx, Ma, Ec, Re, gamma = 128, 4, 0.5, 4.0, 100.0, 1.4
+    ny, nx, Re, gamma = 128, 4, 100.0, 1.4
     u0 = Ma * math.sqrt(gamma)
     TC, TH = 1.0, 1.0 + u0 * u0 / (gamma / (gamma - 1) * Ec)
     y = (np.arange(ny) + 0.5) / ny
@@ -377,9 +383,13 @@ def test_thermal_couette_steady_profile(split, Pr):
     th = (T - TC) / (TH - TC)
     ref = (y + Pr * Ec / 2 * y * (1 - y))[:, None]
     err = float(np.abs(th - ref).max()) / float(ref.max())
-    print(f"[couette] split {split} Pr {Pr}: max error {err:.2e} of the peak", flush=True)
+    print(f"[couette] Ma {Ma} Ec {Ec} split {split} Pr {Pr}: max error {err:.2e} of the peak", flush=True)
+    assert np.isfinite(th).all()
     assert np.abs(th - th[:, :1]).max() < 1e-12  # x-independent
-    assert err < (0.03 if (split == 1 and Pr == 2.0) else 0.01)
+    if Ma > 1:
+        assert err < 0.05
+    else:
+        assert err < (0.03 if (split == 1 and Pr == 2.0) else 0.01)
 
 
 # ---------------------------------------------------------------- Sod shock tube (Sec. IV, conservation)
