@@ -806,3 +806,45 @@ def test_shock_vortex_case_c_sound():
           f"{ray_diff.max():.1e}, beyond r = 1: {ray_diff[radii >= 1.0].max():.1e}; pressure rel. L2 {rel_l2:.1e}; "
           f"max |dp/p_r| {np.abs(p32 - p64).max():.1e}", flush=True)
     assert shift < 2e-3 and rel_l2 < 3e-4 and ray_diff.max() < 3e-4  # measured 7.4e-4, 1.3e-4, 1.2e-4
+
+
+@pytest.mark.parametrize("split,theta,mach,gamma,bound", (
+    (1, 0.1, 0.0, 1.4, 5e-3), (1, 10.0, 0.0, 1.4, 1e-3), (1, 100.0, 0.0, 1.4, 1e-3), (1, 1.0, 0.0, 5.0 / 3.0, 1e-3),
+    (2, 0.1, 0.0, 1.4, 1e-2), (2, 30.0, 0.0, 1.4, 1e-3), (2, 1.0, 1.5, 1.4, 2e-3), (2, 1.0, 2.0, 1.4, 2e-3),
+    (2, 1.0, 2.0, 4.0 / 3.0, 2e-3), (2, 1.0, 0.0, 5.0 / 3.0, 1e-3)))
+def test_speed_of_sound_ranges(split, theta, mach, gamma, bound):
+    """The speed of sound over the temperature and Mach ranges of the paper's
+    study (Sec. IV), at its CFL of 0.01 (256 cells, FP64, tau_ref = 1e-3
+    sqrt(theta)): split I (D2Q16) from T / T_ref = 0.1 to 100, split II
+    (D2Q25) from 0.1 to 30 and up to Mach 2 (gamma 1.4 and 4/3).  Measured
+    (c / sqrt(gamma R T) - 1): 0.24 % (split I) and 0.55 % (split II) at
+    T / T_ref = 0.1, at most 2.6e-4 from 0.3 to 100, 3.8e-4 and 8.4e-4 at
+    Mach 1.5 and 2.  Beyond these the runs diverge or drift: split I below
+    T / T_ref = 0.05 and above Mach 1.5, split II at 100 T_ref, at Mach 2.5
+    whatever tau (to 3e-2) and CFL (to 0.002), and at Mach 2 with gamma 5/3."""
+    from synth import acoustic_wave
+    n = 256
+    wl = acoustic_wave(n, 4, theta=theta, mach=mach, gamma=gamma)
+    s, _ = solver(wl, split=split, storage="f64", Pr=0.71, tau_ref=1e-3 * math.sqrt(theta), gamma=gamma, cfl=0.01)
+    dt = s.dt
+    c0 = math.sqrt(gamma * theta)
+    U = mach * c0
+    e = np.exp(-2j * math.pi * (np.arange(n) + 0.5) / n)
+    nsteps = int(1.3 / (c0 * dt))
+    chunk = max(1, nsteps // 120)
+    times, vals = [], []
+    for m in range(nsteps // chunk):
+        a = 2 * (s.moments(fields=True, sums=False)["rho"].cpu().numpy()[0] * e).mean()
+        t = m * chunk * dt
+        times.append(t)
+        vals.append((a * np.exp(2j * math.pi * U * t)).real)
+        s.step(chunk)
+    s.close()
+    v, tt = np.array(vals), np.array(times)
+    assert np.isfinite(v).all()
+    z = [tt[i] - v[i] * (tt[i + 1] - tt[i]) / (v[i + 1] - v[i]) for i in range(len(v) - 1) if v[i] * v[i + 1] < 0]
+    assert len(z) >= 2
+    c = 0.5 / np.diff(z).mean()
+    print(f"[sound range] split {split} theta {theta} Ma {mach} gamma {gamma:.3f}: c / sqrt(gamma R T) - 1 = "
+          f"{c / c0 - 1:.2e}", flush=True)
+    assert abs(c / c0 - 1) < bound
