@@ -811,17 +811,21 @@ def test_shock_vortex_case_c_sound():
 @pytest.mark.parametrize("split,theta,mach,gamma,bound", (
     (1, 0.1, 0.0, 1.4, 5e-3), (1, 10.0, 0.0, 1.4, 1e-3), (1, 100.0, 0.0, 1.4, 1e-3), (1, 1.0, 0.0, 5.0 / 3.0, 1e-3),
     (2, 0.1, 0.0, 1.4, 1e-2), (2, 30.0, 0.0, 1.4, 1e-3), (2, 1.0, 1.5, 1.4, 2e-3), (2, 1.0, 2.0, 1.4, 2e-3),
-    (2, 1.0, 2.0, 4.0 / 3.0, 2e-3), (2, 1.0, 0.0, 5.0 / 3.0, 1e-3)))
+    (2, 1.0, 2.0, 4.0 / 3.0, 2e-3), (2, 1.0, 0.0, 5.0 / 3.0, 1e-3), (2, 0.5, 2.5, 1.4, 2e-3),
+    (2, 0.5, 2.0, 5.0 / 3.0, 2e-3), (1, 0.3, 2.0, 1.4, 2e-3)))
 def test_speed_of_sound_ranges(split, theta, mach, gamma, bound):
     """The speed of sound over the temperature and Mach ranges of the paper's
     study (Sec. IV), at its CFL of 0.01 (256 cells, FP64, tau_ref = 1e-3
     sqrt(theta)): split I (D2Q16) from T / T_ref = 0.1 to 100, split II
-    (D2Q25) from 0.1 to 30 and up to Mach 2 (gamma 1.4 and 4/3).  Measured
+    (D2Q25) from 0.1 to 30 and up to Mach 2 (gamma 1.4 and 4/3); colder
+    flows go further: split II at Mach 2.5 (T / T_ref = 0.5) and Mach 2 with
+    gamma 5/3, split I at Mach 2 (T / T_ref = 0.3).  Measured
     (c / sqrt(gamma R T) - 1): 0.24 % (split I) and 0.55 % (split II) at
-    T / T_ref = 0.1, at most 2.6e-4 from 0.3 to 100, 3.8e-4 and 8.4e-4 at
-    Mach 1.5 and 2.  Beyond these the runs diverge or drift: split I below
-    T / T_ref = 0.05 and above Mach 1.5, split II at 100 T_ref, at Mach 2.5
-    whatever tau (to 3e-2) and CFL (to 0.002), and at Mach 2 with gamma 5/3."""
+    T / T_ref = 0.1, at most 2.6e-4 from 0.3 to 100, 3.5e-4 to 8.4e-4 at
+    Mach 1.5 to 2.5.  Beyond these the runs diverge or drift: split I below
+    T / T_ref = 0.05 and at Mach 2 at T_ref, split II at 100 T_ref, at Mach
+    2.5 at T_ref whatever tau (to 3e-2) and CFL (to 0.002), at Mach 3 at every
+    temperature tried (0.2 to 1 T_ref), and at any Mach >= 2 at 0.2 T_ref."""
     from synth import acoustic_wave
     n = 256
     wl = acoustic_wave(n, 4, theta=theta, mach=mach, gamma=gamma)
