@@ -61,8 +61,8 @@ extern "C" {
 
 /* DVBM_F32_DEV keeps float32's bytes but stores the deviation: near the rest
  * state its values are small, so a rounding of the stored value is that much
- * finer than one of X itself.  The column-sweep kernel also does its
- * arithmetic in deviation units; the adjoint does not take this format. */
+ * finer than one of X itself.  The step kernels also do their arithmetic
+ * in deviation units; the adjoint does not take this format. */
 enum dvbm_storage { DVBM_F64 = 0, DVBM_F32 = 1, DVBM_BF16_DEV = 2, DVBM_FP16_DEV = 3, DVBM_F32_DEV = 4 };
 /* Boundaries: periodic; zero-gradient (two ghost layers copy the nearest
  * interior cell); DVBM_WALL (bc_y only): no-slip walls on the faces below row

@@ -315,8 +315,9 @@ __device__ inline void collision_coeffs(const MomentsT<V>& m, const KParams& kp,
 }
 
 // out[i] += w_i sum_{p+q<=N} b[p][q] He_p(xi_a) He_q(xi_b) / (p! q!),  i = a N1 + b
-// (Eq. Grad-Hermite-expansion-static in normalised units).
-template <int N1, int N, class R, int BD>
+// (Eq. Grad-Hermite-expansion-static in normalised units); without the
+// weight w_i when WEIGHTED is false (deviation units X / w).
+template <int N1, int N, class R, int BD, bool WEIGHTED = true>
 __device__ inline void expand_add(const R (&b)[BD][BD], R* out) {
   using L = GH<N1>;
 #pragma unroll
@@ -335,7 +336,7 @@ __device__ inline void expand_add(const R (&b)[BD][BD], R* out) {
 #pragma unroll
     for (int xa = 0; xa < N1; ++xa) {
       const double xv = L::xi(xa);
-      const double wab = L::w(xa) * L::w(yb);
+      const double wab = WEIGHTED ? L::w(xa) * L::w(yb) : 1.0;
       R acc = out[xa * N1 + yb];
 #pragma unroll
       for (int p = 0; p <= N; ++p) {

@@ -152,18 +152,22 @@ __device__ inline void cell_update(const typename S::T* __restrict__ src, typena
   R bf[5][5], bg[3][3], om1;
   collision_coeffs<SPLIT, PRM, R>(m, kp, kp.om_scale, kp.Pr, bf, bg, om1);
 
-  // collision: (1 - om1) X + expansion of b.  For 32/64-bit storage X holds
-  // the increment -om1 X + expansion, added to the stored value once at the
-  // end (one rounding at the magnitude of X)
-  const R keep = R(1) - om1;
-  const R scale = S::dev ? keep : -om1;
+  // collision: (1 - om1) X + expansion of b.  X then holds the increment,
+  // added to the stored value once at the end (one rounding at the stored
+  // value's magnitude): -om1 X + expansion for values, and in deviation units
+  // d = X / w - r,  -om1 (r + d) + expansion / w  for the deviation formats.
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    X[0][i] *= scale;
-    X[1][i] *= scale;
+    if constexpr (S::dev) {
+      X[0][i] = -om1 * (R(1) + xs[0][i]);
+      X[1][i] = -om1 * (R(g_ref_over_w<SPLIT>(kp, i)) + xs[1][i]);
+    } else {
+      X[0][i] *= -om1;
+      X[1][i] *= -om1;
+    }
   }
-  expand_add<N1, Set<SPLIT>::NF>(bf, X[0]);
-  expand_add<N1, 2>(bg, X[1]);
+  expand_add<N1, Set<SPLIT>::NF, R, 5, !S::dev>(bf, X[0]);
+  expand_add<N1, 2, R, 3, !S::dev>(bg, X[1]);
 
   // advection: -(dt/dx) v_x (X_{x+1/2} - X_{x-1/2}) - (dt/dy) v_y (X_{y+1/2} - X_{y-1/2})
   const R beta2 = R(kp.beta2);
@@ -200,10 +204,13 @@ __device__ inline void cell_update(const typename S::T* __restrict__ src, typena
         div += ky * R(xb) * dface_pos(ly(oym2, -2), ly(oym1, -1), c0, ly(oyp1, 1), beta2);
       else if (xb < 0.0)
         div += ky * R(xb) * dface_neg(ly(oym1, -1), c0, ly(oyp1, 1), ly(oyp2, 2), beta2);
-      const double w = weight<SPLIT>(i);
-      const R rr = S::dev ? R(d == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i)) : R(0);
-      const R xnew = S::dev ? X[d][i] - R(w) * div : c0 + (X[d][i] - div);
-      Buf<T>::st(rsrc_dst[d], so, o0, S::enc(xnew, R(1.0 / w), rr));
+      // the flux of the deviations is that of the values over w (the
+      // reconstruction commutes with shifts and scalings)
+      const R xnew = c0 + (X[d][i] - div);
+      if constexpr (S::dev)
+        Buf<T>::st(rsrc_dst[d], so, o0, S::enc_dev(xnew));
+      else
+        Buf<T>::st(rsrc_dst[d], so, o0, S::enc(xnew, R(1), R(0)));
     }
   }
 }
@@ -321,7 +328,6 @@ __device__ inline void tile_update(const typename S::T* __restrict__ src, typena
   }
   R bf[5][5], bg[3][3], om1;
   collision_coeffs<SPLIT, PRM, R>(m, kp, kp.om_scale, kp.Pr, bf, bg, om1);
-  const R keep = R(1) - om1;
   const R beta2 = R(kp.beta2);
   const R kx = R(kp.kx), ky = R(kp.ky);
 
@@ -380,15 +386,16 @@ __device__ inline void tile_update(const typename S::T* __restrict__ src, typena
       const R c0 = xs[d][i];
       const uint32_t so = i * plane_bytes;
       const R rr = S::dev ? R(d == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i)) : R(0);
-      const R X = S::dev ? R(w) * (rr + c0) : c0;
-      // collision: (1 - om1) X + w_i sum_p He_p(xi_a)/p! c_p; for 32/64-bit
-      // storage the increment is summed first and added to X once
-      R xn = S::dev ? keep * X : -om1 * X;
+      // collision: (1 - om1) X + w_i sum_p He_p(xi_a)/p! c_p.  The increment
+      // is summed first and added to the stored value once: -om1 X + ... for
+      // values, -om1 (r + d) + sum_p He_p c_p in deviation units d = X/w - r
+      R xn = -om1 * (rr + c0);
+      constexpr double wx = S::dev ? 1.0 : w;
 #pragma unroll
       for (int p = 0; p <= NMAX; ++p) {
         if (p > N) continue;
         const double h = hn(p, xv);
-        if (h != 0.0) xn += R(w * h) * c[p];
+        if (h != 0.0) xn += R(wx * h) * c[p];
       }
       // advection: -(dt/dx) v_x (X_{x+1/2} - X_{x-1/2}) - (dt/dy) v_y (X_{y+1/2} - X_{y-1/2})
       R div = R(0);
@@ -400,11 +407,13 @@ __device__ inline void tile_update(const typename S::T* __restrict__ src, typena
         div += ky * R(xb) * dface_pos(buf[me - 2 * W], buf[me - W], c0, buf[me + W], beta2);
       else if (xb < 0.0)
         div += ky * R(xb) * dface_neg(buf[me - W], c0, buf[me + W], buf[me + 2 * W], beta2);
-      if constexpr (S::dev)
-        xn -= R(w) * div;
-      else
-        xn = X + (xn - div);
-      if (valid) Buf<T>::st(rsrc_dst[d], so, o0, S::enc(xn, R(1.0 / w), rr));
+      xn = c0 + (xn - div);  // deviations share the flux form of the values (over w)
+      if (valid) {
+        if constexpr (S::dev)
+          Buf<T>::st(rsrc_dst[d], so, o0, S::enc_dev(xn));
+        else
+          Buf<T>::st(rsrc_dst[d], so, o0, S::enc(xn, R(1), R(0)));
+      }
     });
   });
   (void)PL;

@@ -523,22 +523,24 @@ def test_thermal_wave_4096_precision_2000_steps():
     a step moves a population by a few float32 ulps in all, so float32 values
     drift from the float64-storage run by 2e-5 (relative L2, growing with the
     step count), while float32 deviations from the rest state, a twentieth of
-    the values' size here, stay within 1e-5."""
+    the values' size here, stay within 1e-5, in the column sweep and in the
+    per-cell kernel alike."""
     wl = thermal_wave(4096, seed=0)
     out = {}
-    for storage in ("f64", "f32", "f32_dev"):
-        print(f"[thermal 4096] {storage}", flush=True)
-        s, _ = solver(wl, split=2, storage=storage, Pr=0.5, tau_ref=5e-5)
+    for storage, kernel in (("f64", "auto"), ("f32", "auto"), ("f32_dev", "auto"), ("f32_dev", "cell")):
+        print(f"[thermal 4096] {storage} {kernel}", flush=True)
+        s, _ = solver(wl, split=2, storage=storage, Pr=0.5, tau_ref=5e-5, kernel=kernel)
         s.step(2000)
         m = s.moments(fields=True, sums=False)
-        out[storage] = {k: m[k] for k in ("rho", "T")}
+        out[storage if kernel == "auto" else f"{storage}_{kernel}"] = {k: m[k] for k in ("rho", "T")}
         s.close()
         del s, m
         torch.cuda.empty_cache()
-    errs = {(st, k): rel(out[st][k], out["f64"][k]) for st in ("f32", "f32_dev") for k in ("rho", "T")}
+    errs = {(st, k): rel(out[st][k], out["f64"][k]) for st in ("f32", "f32_dev", "f32_dev_cell") for k in ("rho", "T")}
     print("[thermal 4096] relative L2 against f64 after 2000 steps: "
           + ", ".join(f"{st} {k} {v:.2e}" for (st, k), v in errs.items()), flush=True)
     assert errs["f32_dev", "rho"] < 1e-5 and errs["f32_dev", "T"] < 1e-5
+    assert errs["f32_dev_cell", "rho"] < 1e-5 and errs["f32_dev_cell", "T"] < 1e-5
     assert errs["f32", "rho"] < 5e-5 and errs["f32", "T"] < 5e-5
 
 
