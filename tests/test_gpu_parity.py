@@ -747,7 +747,9 @@ def test_shock_vortex_case_c_sound():
       pressure at t* = 6 (8,800 steps), within what 8,800 float32 steps
       through a shock accumulate: relative L2 of the pressure 1.3e-4, largest
       at the shock (a sub-cell shift of it), and 1.2e-4 of p_r along the
-      ray (2 % of the precursor's peak)."""
+      ray (2 % of the precursor's peak).  Float32 deviations do no better
+      here (1.5e-4): at Mach 1.2 the deviation from the rest state is as
+      large as the value."""
     from paper_2510_04197_amd import diagnostics as Dg
     from synth import shock_vortex
     wl = shock_vortex(1680, 1440, 1.2, 0.25, 1.0 / 24.0, Lx=28.0, Ly=24.0, x_shock=8.0)
@@ -755,7 +757,7 @@ def test_shock_vortex_case_c_sound():
     c_ratio = math.sqrt(ph["T_post"])  # c_r / c_l with T_l = 1
     radii = np.arange(0.0, 13.0, 0.05)
     rays, centres, fields6 = {}, {}, {}
-    for storage, t_stars in (("f32", (4.0, 6.0, 8.0, 10.0)), ("f64", (6.0,))):
+    for storage, t_stars in (("f32", (4.0, 6.0, 8.0, 10.0)), ("f64", (6.0,)), ("f32_dev", (6.0,))):
         print(f"[shock-vortex] case C, {storage}", flush=True)
         s, p = solver(wl, split=2, storage=storage, Pr=0.75, gamma=1.4, tau_ref=ph["mu"], bc_x="zero_gradient",
                       bc_y="periodic", cfl=0.1)
@@ -808,6 +810,11 @@ def test_shock_vortex_case_c_sound():
           f"{ray_diff.max():.1e}, beyond r = 1: {ray_diff[radii >= 1.0].max():.1e}; pressure rel. L2 {rel_l2:.1e}; "
           f"max |dp/p_r| {np.abs(p32 - p64).max():.1e}", flush=True)
     assert shift < 2e-3 and rel_l2 < 3e-4 and ray_diff.max() < 3e-4  # measured 7.4e-4, 1.3e-4, 1.2e-4
+    pd = fields6["f32_dev"] + 1.0
+    rel_dev = float(np.linalg.norm(pd - p64) / np.linalg.norm(p64))
+    ray_dev = np.abs(Dg.ray(fields6["f32_dev"], c64, 45.0, radii, wl.dx, wl.dy) - rays["f64", 6.0]).max()
+    print(f"[shock-vortex] f32_dev vs f64 at t* 6: pressure rel. L2 {rel_dev:.1e}, along the ray {ray_dev:.1e}", flush=True)
+    assert rel_dev < 3e-4 and ray_dev < 3e-4
 
 
 @pytest.mark.parametrize("split,theta,mach,gamma,bound", (
