@@ -728,9 +728,10 @@ def test_sound_attenuation(split, Pr, gamma, mach):
 
 
 # ---------------------------------------------------------------- shock-vortex sound diagnostics (Sec. IV)
-def test_shock_vortex_case_c_sound():
-    """Case C of the shock-vortex interaction (Ma_s 1.2, Ma_v 0.25, Re_v 800,
-    Pr 0.75, split II) on the 28 x 24 r_v domain at 60 cells per r_v, shock at
+@pytest.mark.parametrize("case,mach_s,mach_v", (("C", 1.2, 0.25), ("G", 1.29, 0.39)))
+def test_shock_vortex_sound(case, mach_s, mach_v):
+    """Cases C (Ma_s 1.2, Ma_v 0.25) and G (Ma_s 1.29, Ma_v 0.39) of the
+    shock-vortex interaction (Re_v 800, Pr 0.75, split II) on the 28 x 24 r_v domain at 60 cells per r_v, shock at
     x = 8, vortex at (6, 12), zero-gradient x boundaries; CFL 0.1 (at CFL 0.2
     the post-shock dt / tau_1 is 1.2 and the run diverges).  Properties that
     hold without the reference DNS data:
@@ -740,10 +741,13 @@ def test_shock_vortex_case_c_sound():
       sound move outwards at the post-shock sound speed, approached from above
       as the fronts grow (a front centred off the vortex centre runs ahead of
       c_r along the ray by a share that falls as its radius grows): between
-      t* = 8 and 10 within 0 to 5 % above c_r / c_l per unit t*, and slower
-      than between t* = 6 and 8 (measured 3.5 % and 0.8 % above);
+      t* = 8 and 10 within -2 % to +5 % of c_r / c_l per unit t*, and slower
+      than between t* = 6 and 8 (measured in case C 3.6 % and 0.1 % above,
+      in case G 3.2 % above and 0.9 % below: a weak wave of amplitude p'/p
+      runs at c (1 + (gamma + 1)/(2 gamma) p'/p), and case G's second sound
+      is a rarefaction of about 1 %);
     * ahead of the precursor (r from 9 to 13 r_v at t* = 6) the field is quiet;
-    * float32 and float64 storage give the same vortex centre and sound
+    * (case C) float32 and float64 storage give the same vortex centre and sound
       pressure at t* = 6 (8,800 steps), within what 8,800 float32 steps
       through a shock accumulate: relative L2 of the pressure 1.3e-4, largest
       at the shock (a sub-cell shift of it), and 1.2e-4 of p_r along the
@@ -752,13 +756,14 @@ def test_shock_vortex_case_c_sound():
       large as the value."""
     from paper_2510_04197_amd import diagnostics as Dg
     from synth import shock_vortex
-    wl = shock_vortex(1680, 1440, 1.2, 0.25, 1.0 / 24.0, Lx=28.0, Ly=24.0, x_shock=8.0)
+    wl = shock_vortex(1680, 1440, mach_s, mach_v, 1.0 / 24.0, Lx=28.0, Ly=24.0, x_shock=8.0)
     ph = wl.phys
     c_ratio = math.sqrt(ph["T_post"])  # c_r / c_l with T_l = 1
     radii = np.arange(0.0, 13.0, 0.05)
     rays, centres, fields6 = {}, {}, {}
-    for storage, t_stars in (("f32", (4.0, 6.0, 8.0, 10.0)), ("f64", (6.0,)), ("f32_dev", (6.0,))):
-        print(f"[shock-vortex] case C, {storage}", flush=True)
+    runs = (("f32", (4.0, 6.0, 8.0, 10.0)), ("f64", (6.0,)), ("f32_dev", (6.0,)))
+    for storage, t_stars in runs if case == "C" else runs[:1]:
+        print(f"[shock-vortex] case {case}, {storage}", flush=True)
         s, p = solver(wl, split=2, storage=storage, Pr=0.75, gamma=1.4, tau_ref=ph["mu"], bc_x="zero_gradient",
                       bc_y="periodic", cfl=0.1)
         dt, n, c = s.dt, 0, ph["centre"]
@@ -779,7 +784,7 @@ def test_shock_vortex_case_c_sound():
 
     (t4, c4), (t10, c10) = centres["f32", 4.0], centres["f32", 10.0]
     speed = (c10[0] - c4[0]) / (t10 - t4)
-    print(f"[shock-vortex] vortex speed / u_r - 1 = {speed / ph['u_post'] - 1:.2e}", flush=True)
+    print(f"[shock-vortex] case {case}: vortex speed / u_r - 1 = {speed / ph['u_post'] - 1:.2e}", flush=True)
     assert abs(speed / ph["u_post"] - 1) < 5e-3
 
     def peak(pr, lo, hi, sign):
@@ -791,15 +796,19 @@ def test_shock_vortex_case_c_sound():
     for name, lo, hi, sign in (("precursor", 4.5, 12.5, 1), ("second sound", 2.5, 9.5, -1)):
         r6, r8, r10 = (peak(rays["f32", ts], lo, hi, sign) for ts in (6.0, 8.0, 10.0))
         early, late = (r8 - r6) / 2 / c_ratio, (r10 - r8) / 2 / c_ratio
-        print(f"[shock-vortex] {name} at r/r_v {r6:.3f} {r8:.3f} {r10:.3f}; speed / c_r: {early:.4f} then {late:.4f}",
-              flush=True)
-        assert 1.0 <= late < 1.05 and late < early
+        amp = float(np.interp(r10, radii, rays["f32", 10.0]) / (1.0 + np.interp(r10, radii, rays["f32", 10.0])))
+        print(f"[shock-vortex] case {case}: {name} at r/r_v {r6:.3f} {r8:.3f} {r10:.3f}; speed / c_r: {early:.4f} "
+              f"then {late:.4f}; amplitude p'/p at t* 10 {amp:+.2e}", flush=True)
+        assert 0.98 <= late < 1.05 and late < early
 
     pr6 = rays["f32", 6.0]
     front = peak(pr6, 4.5, 12.5, 1)
     ahead = np.abs(pr6[radii >= 9.0]).max()
-    print(f"[shock-vortex] t* 6: precursor {pr6.max():.2e} at {front:.2f}; max |p_sound| ahead {ahead:.1e}", flush=True)
+    print(f"[shock-vortex] case {case}, t* 6: precursor {pr6.max():.2e} at {front:.2f}; max |p_sound| ahead "
+          f"{ahead:.1e}", flush=True)
     assert front < 7.5 and ahead < 0.1 * pr6.max()
+    if case != "C":
+        return
 
     c64 = centres["f64", 6.0][1]
     shift = math.hypot(c64[0] - centres["f32", 6.0][1][0], c64[1] - centres["f32", 6.0][1][1])
