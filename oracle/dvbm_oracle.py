@@ -97,6 +97,7 @@ class Config:
     T_ref: float = 1.0
     beta: float = 1.2
     cfl: float = 0.01
+    dt: float = 0.0           # > 0: a fixed time step in place of the CFL rule
     wall_T: tuple = (1.0, 1.0)    # bc_y == WALL: temperatures of the lower and upper wall
     wall_ux: tuple = (0.0, 0.0)   # bc_y == WALL: x velocities of the lower and upper wall
 
@@ -496,10 +497,26 @@ def advection(X: torch.Tensor, v: torch.Tensor, cfg: Config, dt, ghosts_y=None) 
 # Time step, initial state, one update, diagnostics
 # --------------------------------------------------------------------------
 def time_step(rho, u, T, cfg: Config) -> float:
-    """``dt = CFL min(dx, dy) / max(|u| + c_s)`` over the initial fields (Sec. III A 3)."""
+    """``dt = CFL min(dx, dy) / max(|u| + c_s)`` over the initial fields (Sec. III A 3),
+    with the adiabatic sound speed ``c_s = sqrt(gamma R T)``; a given ``cfg.dt > 0``
+    is used as it stands."""
+    if cfg.dt > 0:
+        return float(cfg.dt)
     rho, u, T = (torch.as_tensor(x, dtype=DT) for x in (rho, u, T))
     speed = torch.sqrt((u * u).sum(-1)) + torch.sqrt(cfg.gamma * cfg.R * T)
     return float(cfg.cfl * min(cfg.dx, cfg.dy) / speed.max())
+
+
+def max_relaxation_rate(rho, T, cfg: Config, dt) -> float:
+    """Largest ``dt / tau_1`` over the fields (relaxation times of Sec. II C).
+
+    The collision term of Eq. (finalDiscretePDE) is integrated with forward
+    Euler (Sec. III A); on the relaxation alone one step multiplies
+    ``X - X*`` by ``1 - dt/tau_1``, which stays bounded only while
+    ``dt / tau_1 <= 2``."""
+    rho, T = (torch.as_tensor(x, dtype=DT) for x in (rho, T))
+    tau1, _ = relaxation_times(rho, T, cfg, cfg.tau_ref, cfg.Pr)
+    return float((dt / tau1).max())
 
 
 def initial_state(rho, ux, uy, T, cfg: Config):

@@ -30,7 +30,7 @@ def oracle_cfg(p) -> O.Config:
     return O.Config(nx=p.nx, ny=p.ny, split=p.split, bc_x=inv_bc[p.bc_x], bc_y=inv_bc[p.bc_y],
                     visc_mode=O.CONST_MU if p.visc_mode == 0 else O.CONST_TAU, dx=p.dx, dy=p.dy, R=p.R,
                     gamma=p.gamma, Pr=p.Pr, tau_ref=p.tau_ref, p_ref=p.p_ref, T_ref=p.T_ref, beta=p.beta,
-                    cfl=p.cfl, wall_T=(p.wall_T[0], p.wall_T[1]), wall_ux=(p.wall_ux[0], p.wall_ux[1]))
+                    cfl=p.cfl, dt=p.dt, wall_T=(p.wall_T[0], p.wall_T[1]), wall_ux=(p.wall_ux[0], p.wall_ux[1]))
 
 
 def solver(wl, **kw):
@@ -56,6 +56,76 @@ def test_initial_equilibrium(split, storage, tol):
     f, g = oracle_state(s)
     fo, go = O.initial_state(wl.rho, wl.ux, wl.uy, wl.T, oracle_cfg(p))
     assert rel(f, fo) < tol and rel(g, go) < tol
+
+
+# ---------------------------------------------------------------- time step (Sec. III A 3)
+def _dt_case(case):
+    """Initial fields and parameters of the time-step cases: smooth random
+    fields, the Mach-1 vortex, a shock-vortex field with zero-gradient x, the
+    Sod tube and a flow between no-slip walls."""
+    if case == "smooth":
+        return smooth_random(70, 37, seed=21), dict(split=2, tau_ref=0.02, cfl=0.1)
+    if case == "vortex":
+        return isentropic_vortex(128, seed=3), dict(split=2, tau_ref=0.02)
+    if case == "shock":
+        wl = shock_vortex(256, 128, mach_s=1.2, mach_v=0.25, r_frac=0.075, gamma=5.0 / 3.0)
+        return wl, dict(split=2, gamma=5.0 / 3.0, bc_x="zero_gradient", tau_ref=0.02, Pr=2.0)
+    if case == "sod":
+        return sod_tube(128, 4), dict(split=1, tau_ref=0.02, cfl=0.2, Pr=0.5)
+    wl = smooth_random(33, 20, seed=22, amp_u=0.3)
+    return wl, dict(split=1, bc_y="wall", wall_T=(0.9, 1.2), wall_ux=(0.0, 0.5), tau_ref=0.02, cfl=0.05, R=1.7,
+                    T_ref=1.3)
+
+
+@pytest.mark.parametrize("storage", ("f64", "f32"))
+@pytest.mark.parametrize("case", ("smooth", "vortex", "shock", "sod", "wall"))
+def test_time_step_matches_oracle(case, storage):
+    """dvbm_init's time step (reduction of |u| + sqrt(gamma R T) over the
+    initial fields) equals the oracle's CFL rule to 1e-15 relative."""
+    wl, kw = _dt_case(case)
+    s, p = solver(wl, storage=storage, **kw)
+    dt_o = O.time_step(wl.rho, np.stack([wl.ux, wl.uy], -1), wl.T, oracle_cfg(p))
+    assert abs(s.dt - dt_o) <= 1e-15 * dt_o, (s.dt, dt_o)
+    s.close()
+
+
+def test_time_step_override():
+    """A given dt > 0 replaces the CFL rule on both sides, bit for bit."""
+    wl, kw = _dt_case("smooth")
+    s, p = solver(wl, storage="f64", dt=3.25e-5, **kw)
+    assert s.dt == 3.25e-5 == O.time_step(wl.rho, np.stack([wl.ux, wl.uy], -1), wl.T, oracle_cfg(p))
+    s.close()
+
+
+@pytest.mark.parametrize("rule", ("dt", "cfl"))
+@pytest.mark.parametrize("Pr", (0.5, 1.0, 2.0))
+@pytest.mark.parametrize("visc_mode", ("const_mu", "const_tau"))
+def test_stiffness_threshold(visc_mode, Pr, rule):
+    """dvbm_init rejects a step with dt / tau_1 > 2 on the initial fields
+    (ESTIFF) and accepts one just below: 1e-9 either side of the oracle's
+    threshold, with the step given (rule 'dt') or from the CFL rule with
+    tau_ref moved across the threshold (rule 'cfl')."""
+    wl = smooth_random(16, 12, seed=23, amp_rho=0.2, amp_T=0.2)
+    base = dict(split=2, storage="f64", visc_mode=visc_mode, Pr=Pr, cfl=0.1, p_ref=1.3, R=1.2)
+    cfg = oracle_cfg(make_params(wl.nx, wl.ny, dx=wl.dx, dy=wl.dy, tau_ref=1e-3, **base))
+    if rule == "dt":
+        dt_c = 2.0 / O.max_relaxation_rate(wl.rho, wl.T, cfg, 1.0)
+        cases = [(dict(tau_ref=1e-3, dt=dt_c * (1 - 1e-9)), True), (dict(tau_ref=1e-3, dt=dt_c * (1 + 1e-9)), False)]
+    else:
+        dt = O.time_step(wl.rho, np.stack([wl.ux, wl.uy], -1), wl.T, cfg)
+        tau_c = 1e-3 * O.max_relaxation_rate(wl.rho, wl.T, cfg, dt) / 2.0
+        cases = [(dict(tau_ref=tau_c * (1 + 1e-9)), True), (dict(tau_ref=tau_c * (1 - 1e-9)), False)]
+    for extra, ok in cases:
+        p = make_params(wl.nx, wl.ny, dx=wl.dx, dy=wl.dy, **base, **extra)
+        c = oracle_cfg(p)
+        rate = O.max_relaxation_rate(wl.rho, wl.T, c, O.time_step(wl.rho, np.stack([wl.ux, wl.uy], -1), wl.T, c))
+        assert (rate <= 2.0) == ok, (rate, extra)
+        if ok:
+            Solver(p, wl.rho, wl.ux, wl.uy, wl.T, device=DEV).close()
+        else:
+            with pytest.raises(DVBMError) as e:
+                Solver(p, wl.rho, wl.ux, wl.uy, wl.T, device=DEV)
+            assert e.value.code == dvbm.DVBM_ESTIFF
 
 
 # ---------------------------------------------------------------- multi-step parity, small grids

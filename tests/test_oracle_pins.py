@@ -678,3 +678,54 @@ def test_sound_attenuation(split, Pr, gamma):
         f, g = O.run(f, g, cfg, dt, chunk)
     measured = -np.polyfit(np.array(ts), np.array(lr), 1)[0] / (k * k)
     assert abs(measured - (G - 0.5 * c * c * dt)) < 0.03 * G, (measured, G)
+
+
+# ---------------------------------------------------------------- time step (Sec. III A 3)
+def _speed_field():
+    """5 x 3 cells, gamma = 1.6, R = 1, whose largest |u| + sqrt(gamma R T) is
+    known by hand: the cell (y=1, x=3) has u = (3, 4) and T = 2.5, so
+    |u| = 5 and c_s = sqrt(4) = 2, speed 7.  Competitors: a hot cell at rest
+    (T = 10, speed 4) and a fast cold one (u = (0, 6), T = 0.1, speed 6.4);
+    the rest of the grid has u = 0, T = 1 (speed 1.26)."""
+    ny, nx = 3, 5
+    rho = np.full((ny, nx), 1.3)
+    T = np.ones((ny, nx))
+    u = np.zeros((ny, nx, 2))
+    u[1, 3] = (3.0, 4.0)
+    T[1, 3] = 2.5
+    T[0, 0] = 10.0
+    u[2, 1] = (0.0, 6.0)
+    T[2, 1] = 0.1
+    return rho, u, T
+
+
+def test_time_step_by_hand():
+    """dt = CFL min(dx, dy) / max(|u| + c_s) (Sec. III A 3): with CFL 0.35,
+    dx = 0.1 and dy = 0.05 the rule gives 0.35 * 0.05 / 7 = 0.0025; the smaller
+    cell size and the largest speed, not a mean, set it."""
+    rho, u, T = _speed_field()
+    cfg = O.Config(nx=5, ny=3, gamma=1.6, R=1.0, dx=0.1, dy=0.05, cfl=0.35)
+    assert abs(O.time_step(rho, u, T, cfg) - 0.0025) <= 1e-15 * 0.0025
+    cfg = O.Config(nx=5, ny=3, gamma=1.6, R=1.0, dx=0.02, dy=0.05, cfl=0.35)
+    assert abs(O.time_step(rho, u, T, cfg) - 0.001) <= 1e-15 * 0.001
+    # R scales the sound speed: R = 4 doubles c_s (cell (1, 3): 5 + 4 = 9; cell (0, 0): 8)
+    cfg = O.Config(nx=5, ny=3, gamma=1.6, R=4.0, dx=0.1, dy=0.05, cfl=0.36)
+    assert abs(O.time_step(rho, u, T, cfg) - 0.002) <= 1e-15 * 0.002
+    # a fixed time step replaces the rule
+    cfg = O.Config(nx=5, ny=3, gamma=1.6, dx=0.1, dy=0.05, cfl=0.35, dt=3e-4)
+    assert O.time_step(rho, u, T, cfg) == 3e-4
+
+
+@pytest.mark.parametrize("visc_mode", (O.CONST_MU, O.CONST_TAU))
+@pytest.mark.parametrize("Pr", (0.5, 1.0, 2.0))
+def test_max_relaxation_rate_by_hand(visc_mode, Pr):
+    """dt / tau_1 with the relaxation times of Sec. II C: tau_nu = mu / p
+    (mu = tau_ref p_ref) or tau_ref, and tau_1 = tau_nu / Pr when Pr > 1.  The
+    field's largest pressure is rho R T = 1.3 * 2 * 10 = 26 (the hot cell),
+    so with tau_ref = 1e-3, p_ref = 2 and dt = 1e-5 the rate is
+    1e-5 * 26 / 2e-3 = 0.13 (constant mu) or 1e-2 (constant tau), times Pr
+    when Pr > 1."""
+    rho, _, T = _speed_field()
+    cfg = O.Config(nx=5, ny=3, R=2.0, tau_ref=1e-3, p_ref=2.0, Pr=Pr, visc_mode=visc_mode)
+    want = (0.13 if visc_mode == O.CONST_MU else 1e-2) * (Pr if Pr > 1 else 1.0)
+    assert abs(O.max_relaxation_rate(rho, T, cfg, 1e-5) - want) <= 1e-14 * want
