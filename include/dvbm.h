@@ -227,6 +227,23 @@ int dvbm_adjoint_step(dvbm_handle* h, const void* state_n, const double* lam_np1
 int dvbm_adjoint_step_f32(dvbm_handle* h, const void* state_n, const float* lam_np1, float* lam_n,
                           double* dparams, void* work);
 
+/* dvbm_adjoint_step for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, with no work argument.  The work rows and
+ * the reduction partials live in a fixed scratch array of 16 MiB that the
+ * library holds on each device it runs on until the process ends (its device
+ * address is looked up once per device in dvbm_init); the call itself makes
+ * no allocation and no runtime call besides its kernel launches.  Grids
+ * needing more than the scratch's 16 MiB - 64 KiB of work rows (nx*ny above
+ * 149,211 cells) are rejected with DVBM_EINVAL.  Every call on one device
+ * uses that device's one array: calls that overlap in time on one GPU (other
+ * streams, other threads, other handles) race and give wrong results;
+ * consecutive calls are safe (each clears the counter it needs).  Other
+ * arguments, errors and ordering as for dvbm_adjoint_step (float64
+ * cotangents, f64 and f32 storage).  Asynchronous. */
+int dvbm_adjoint_step_noalloc(dvbm_handle* h, const void* state_n, const double* lam_np1, double* lam_n,
+                              double* dparams);
+
 /* lam = sum of (d field / dX)^T d_field over the macroscopic fields of state
  * (rho, u_x, u_y, T of Eqs. eq_quadratur1-3); any d_* may be NULL (zero).
  * d_* are device float64 arrays of ny*nx.  Asynchronous. */

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/dvbm.h"
@@ -586,6 +587,8 @@ struct dvbm_handle {
   hipStream_t stream;
   double dt;
   mutable int sweep_kseg;  // row ranges per strip of the column-sweep kernel (0: not chosen yet)
+  double* scratch;         // device address of the fixed scratch array on the handle's device (NULL: lookup failed)
+  std::string scratch_err; // why the lookup failed
 };
 
 namespace {
@@ -738,44 +741,48 @@ void step(const dvbm_handle* h, const void* src, void* dst) {
 }
 
 template <int SPLIT, class S, int BCX, int BCY, class LT>
-void adjoint_bc(const dvbm_handle* h, const void* state, const LT* lam1, LT* lam0, double* dparams, double* work);
+void adjoint_bc(const dvbm_handle* h, const void* state, const LT* lam1, LT* lam0, double* dparams, double* work,
+                double* ws);
 
 // Cotangents lam1, lam0 stored as LT (double or float); the arithmetic and the
-// work array are float64.
+// work array are float64.  ws: the reduction area (block partials of
+// d/dtau_ref, d/dPr from offset 0, the block counter at WS_TICKET doubles).
 template <int SPLIT, class S, class LT>
-void adjoint(const dvbm_handle* h, const void* state, const LT* lam1, LT* lam0, double* dparams, double* work) {
+void adjoint(const dvbm_handle* h, const void* state, const LT* lam1, LT* lam0, double* dparams, double* work,
+             double* ws) {
   const int bx = h->p.bc_x, by = h->p.bc_y;
   if (bx == DVBM_PERIODIC && by == DVBM_PERIODIC)
-    adjoint_bc<SPLIT, S, BC_PERIODIC, BC_PERIODIC, LT>(h, state, lam1, lam0, dparams, work);
+    adjoint_bc<SPLIT, S, BC_PERIODIC, BC_PERIODIC, LT>(h, state, lam1, lam0, dparams, work, ws);
   else if (bx == DVBM_ZERO_GRADIENT && by == DVBM_PERIODIC)
-    adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_PERIODIC, LT>(h, state, lam1, lam0, dparams, work);
+    adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_PERIODIC, LT>(h, state, lam1, lam0, dparams, work, ws);
   else if (bx == DVBM_PERIODIC && by == DVBM_ZERO_GRADIENT)
-    adjoint_bc<SPLIT, S, BC_PERIODIC, BC_ZERO_GRADIENT, LT>(h, state, lam1, lam0, dparams, work);
+    adjoint_bc<SPLIT, S, BC_PERIODIC, BC_ZERO_GRADIENT, LT>(h, state, lam1, lam0, dparams, work, ws);
   else
-    adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_ZERO_GRADIENT, LT>(h, state, lam1, lam0, dparams, work);
+    adjoint_bc<SPLIT, S, BC_ZERO_GRADIENT, BC_ZERO_GRADIENT, LT>(h, state, lam1, lam0, dparams, work, ws);
 }
 
 template <int SPLIT, class S, int BCX, int BCY, class LT>
-void adjoint_bc(const dvbm_handle* h, const void* state, const LT* lam1, LT* lam0, double* dparams, double* work) {
+void adjoint_bc(const dvbm_handle* h, const void* state, const LT* lam1, LT* lam0, double* dparams, double* work,
+                double* ws) {
   using T = typename S::T;
   const T* s = static_cast<const T*>(state);
   const double tau = h->p.tau_ref;
-  unsigned* ticket = reinterpret_cast<unsigned*>(h->ws + WS_TICKET);
+  unsigned* ticket = reinterpret_cast<unsigned*>(ws + WS_TICKET);
   const int64_t cells = int64_t(h->p.nx) * h->p.ny;
   const int64_t nb = (cells + RED_THREADS - 1) / RED_THREADS;
   const dim3 grid(unsigned(nb < ADJ_RELAX_BLOCKS ? nb : ADJ_RELAX_BLOCKS)), block(RED_THREADS);
   switch (pr_mode(h->p.Pr)) {
     case PR_UNIT:
       hipLaunchKernelGGL((k_adjoint_relax<SPLIT, S, PR_UNIT, LT>), grid, block, 0, h->stream, s, lam1, work, h->kp, tau,
-                         h->ws, ticket, dparams);
+                         ws, ticket, dparams);
       break;
     case PR_LOW:
       hipLaunchKernelGGL((k_adjoint_relax<SPLIT, S, PR_LOW, LT>), grid, block, 0, h->stream, s, lam1, work, h->kp, tau,
-                         h->ws, ticket, dparams);
+                         ws, ticket, dparams);
       break;
     default:
       hipLaunchKernelGGL((k_adjoint_relax<SPLIT, S, PR_HIGH, LT>), grid, block, 0, h->stream, s, lam1, work, h->kp, tau,
-                         h->ws, ticket, dparams);
+                         ws, ticket, dparams);
       break;
   }
   const int64_t groups = 2 * Set<SPLIT>::N1, nstrips = (h->p.nx + ADJ_STRIP - 1) / ADJ_STRIP;
@@ -793,18 +800,18 @@ void adjoint_bc(const dvbm_handle* h, const void* state, const LT* lam1, LT* lam
 template void dvbm_launch::step<(DVBM_PART - 1) / 5 + 1, DVBM_PART_STORE>(const dvbm_handle*, const void*, void*);
 #if (DVBM_PART - 1) % 5 < 2
 template void dvbm_launch::adjoint<(DVBM_PART - 1) / 5 + 1, DVBM_PART_STORE, double>(
-    const dvbm_handle*, const void*, const double*, double*, double*, double*);
+    const dvbm_handle*, const void*, const double*, double*, double*, double*, double*);
 template void dvbm_launch::adjoint<(DVBM_PART - 1) / 5 + 1, DVBM_PART_STORE, float>(
-    const dvbm_handle*, const void*, const float*, float*, double*, double*);
+    const dvbm_handle*, const void*, const float*, float*, double*, double*, double*);
 #endif
 #else
 #define DVBM_EXTERN_STEP(SPLIT, S) \
   extern template void dvbm_launch::step<SPLIT, S>(const dvbm_handle*, const void*, void*);
 #define DVBM_EXTERN_ADJ(SPLIT, S)                                                                           \
   extern template void dvbm_launch::adjoint<SPLIT, S, double>(const dvbm_handle*, const void*, const double*, \
-                                                              double*, double*, double*);                   \
+                                                              double*, double*, double*, double*);          \
   extern template void dvbm_launch::adjoint<SPLIT, S, float>(const dvbm_handle*, const void*, const float*,   \
-                                                             float*, double*, double*);
+                                                             float*, double*, double*, double*);
 DVBM_EXTERN_STEP(1, StoreF64)
 DVBM_EXTERN_STEP(1, StoreF32)
 DVBM_EXTERN_STEP(1, StoreBF16)
@@ -820,7 +827,44 @@ DVBM_EXTERN_ADJ(1, StoreF32)
 DVBM_EXTERN_ADJ(2, StoreF64)
 DVBM_EXTERN_ADJ(2, StoreF32)
 
+// ------------------------------------------------------------ fixed scratch
+// Device memory of dvbm_adjoint_step_noalloc, for callers that cannot
+// allocate: the reduction area (block partials and block counter, laid out as
+// in the workspace) in the first SCRATCH_WORK_OFFSET bytes, the adjoint work
+// rows after it.  Each device holds its own copy until the process ends.  In
+// host code `scratch` names a host-side stand-in, not device memory: kernels
+// get the device address that hipGetSymbolAddress returns for the device.
+constexpr size_t SCRATCH_BYTES = size_t(16) << 20;
+constexpr size_t SCRATCH_WORK_OFFSET = size_t(64) << 10;
+static_assert(size_t(WS_TICKET + 1) * sizeof(double) <= SCRATCH_WORK_OFFSET, "reduction area exceeds its slot");
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+__global__ void k_clear_counter(unsigned* counter) {
+  if (threadIdx.x == 0) counter[0] = 0u;
+}
+
 namespace {
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+hipError_t scratch_address(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 // Calls F<SPLIT, Store>::run(args...) for the handle's split and storage.
 template <template <int, class> class F, class... A>
@@ -891,8 +935,8 @@ template <int SPLIT, class S>
 struct AdjointOp {
   template <class LT>
   static void run(const dvbm_handle* h, const void* state, const LT* lam1, LT* lam0, double* dparams,
-                  double* work) {
-    dvbm_launch::adjoint<SPLIT, S, LT>(h, state, lam1, lam0, dparams, work);
+                  double* work, double* ws) {
+    dvbm_launch::adjoint<SPLIT, S, LT>(h, state, lam1, lam0, dparams, work, ws);
   }
 };
 
@@ -1035,6 +1079,14 @@ int dvbm_init(const dvbm_params* p, const double* rho, const double* ux, const d
   h->ws = ws;
   h->stream = s;
   h->sweep_kseg = 0;
+  // the fixed scratch of dvbm_adjoint_step_noalloc on this device (set-up only:
+  // that entry point then makes no runtime call besides its launches)
+  h->scratch = nullptr;
+  if (hipError_t es = scratch_address(&h->scratch); es != hipSuccess) {
+    h->scratch = nullptr;
+    h->scratch_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(es);
+    (void)hipGetLastError();
+  }
   hipError_t e = hipMemsetAsync(ws + WS_TICKET, 0, sizeof(double), s);  // the adjoint's block counter
   if (e != hipSuccess) {
     delete h;
@@ -1143,7 +1195,7 @@ int dvbm_adjoint_step(dvbm_handle* h, const void* state_n, const double* lam_np1
   if (!h || !state_n || !lam_np1 || !lam_n || !work) return fail(DVBM_EINVAL, "dvbm_adjoint_step: NULL argument");
   if (lam_np1 == lam_n) return fail(DVBM_EINVAL, "dvbm_adjoint_step: lam_np1 and lam_n must differ");
   if (int rc = adjoint_storage_ok(h, "dvbm_adjoint_step")) return rc;
-  dispatch_adjoint<AdjointOp>(h->p, h, state_n, lam_np1, lam_n, dparams, static_cast<double*>(work));
+  dispatch_adjoint<AdjointOp>(h->p, h, state_n, lam_np1, lam_n, dparams, static_cast<double*>(work), h->ws);
   HIP_TRY(hipGetLastError());
   return DVBM_OK;
 }
@@ -1154,7 +1206,30 @@ int dvbm_adjoint_step_f32(dvbm_handle* h, const void* state_n, const float* lam_
     return fail(DVBM_EINVAL, "dvbm_adjoint_step_f32: NULL argument");
   if (lam_np1 == lam_n) return fail(DVBM_EINVAL, "dvbm_adjoint_step_f32: lam_np1 and lam_n must differ");
   if (int rc = adjoint_storage_ok(h, "dvbm_adjoint_step_f32")) return rc;
-  dispatch_adjoint<AdjointOp>(h->p, h, state_n, lam_np1, lam_n, dparams, static_cast<double*>(work));
+  dispatch_adjoint<AdjointOp>(h->p, h, state_n, lam_np1, lam_n, dparams, static_cast<double*>(work), h->ws);
+  HIP_TRY(hipGetLastError());
+  return DVBM_OK;
+}
+
+int dvbm_adjoint_step_noalloc(dvbm_handle* h, const void* state_n, const double* lam_np1, double* lam_n,
+                              double* dparams) {
+  if (!h || !state_n || !lam_np1 || !lam_n) return fail(DVBM_EINVAL, "dvbm_adjoint_step_noalloc: NULL argument");
+  if (lam_np1 == lam_n) return fail(DVBM_EINVAL, "dvbm_adjoint_step_noalloc: lam_np1 and lam_n must differ");
+  if (int rc = adjoint_storage_ok(h, "dvbm_adjoint_step_noalloc")) return rc;
+  const size_t need = dvbm_adjoint_work_bytes(&h->p);
+  if (need > SCRATCH_BYTES - SCRATCH_WORK_OFFSET)
+    return fail(DVBM_EINVAL, "dvbm_adjoint_step_noalloc: the grid needs " + std::to_string(need) +
+                                 " bytes of work rows, more than the " +
+                                 std::to_string(SCRATCH_BYTES - SCRATCH_WORK_OFFSET) +
+                                 " bytes the fixed scratch holds (at most " +
+                                 std::to_string((SCRATCH_BYTES - SCRATCH_WORK_OFFSET) / (ADJ_WORK_ROWS * 8)) +
+                                 " cells); use dvbm_adjoint_step with a caller work array");
+  if (!h->scratch) return fail(DVBM_EHIP, "dvbm_adjoint_step_noalloc: " + h->scratch_err);
+  double* red = h->scratch;
+  double* work = h->scratch + SCRATCH_WORK_OFFSET / sizeof(double);
+  // the block counter must start at zero (the last block of each call resets it)
+  hipLaunchKernelGGL(k_clear_counter, dim3(1), dim3(64), 0, h->stream, reinterpret_cast<unsigned*>(red + WS_TICKET));
+  dispatch_adjoint<AdjointOp>(h->p, h, state_n, lam_np1, lam_n, dparams, work, red);
   HIP_TRY(hipGetLastError());
   return DVBM_OK;
 }

@@ -69,6 +69,7 @@ SIGNATURES = {
     "dvbm_adjoint_work_bytes": (ctypes.c_size_t, [_PP]),
     "dvbm_adjoint_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "dvbm_adjoint_step_f32": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "dvbm_adjoint_step_noalloc": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "dvbm_adjoint_moments": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "dvbm_adjoint_init": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "dvbm_last_error": (ctypes.c_char_p, []),
@@ -250,6 +251,15 @@ class Solver:
         fn = self.lib.dvbm_adjoint_step if lam.dtype == torch.float64 else self.lib.dvbm_adjoint_step_f32
         _check(fn(self._h(), _ptr(state), _ptr(lam_next), _ptr(lam), _ptr(dparams) if dparams is not None else None,
                   _ptr(self._adj_work)))
+
+    def adjoint_step_noalloc(self, state: torch.Tensor, lam_next: torch.Tensor, lam: torch.Tensor,
+                             dparams: torch.Tensor | None = None):
+        """:meth:`adjoint_step` (float64 cotangents) through ``dvbm_adjoint_step_noalloc``: no work
+        array; the library's fixed per-device scratch holds it (grids up to 149,211 cells)."""
+        if lam_next.dtype != torch.float64 or lam.dtype != torch.float64:
+            raise TypeError("lam_next and lam must be float64")
+        _check(self.lib.dvbm_adjoint_step_noalloc(self._h(), _ptr(state), _ptr(lam_next), _ptr(lam),
+                                                  _ptr(dparams) if dparams is not None else None))
 
     def adjoint_moments(self, state: torch.Tensor, d_rho=None, d_ux=None, d_uy=None, d_T=None) -> torch.Tensor:
         """Cotangent of the populations of ``state`` from cotangents of its fields."""
