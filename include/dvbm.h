@@ -62,7 +62,8 @@ extern "C" {
 /* DVBM_F32_DEV keeps float32's bytes but stores the deviation: near the rest
  * state its values are small, so a rounding of the stored value is that much
  * finer than one of X itself.  The step kernels also do their arithmetic
- * in deviation units; the adjoint does not take this format. */
+ * in deviation units.  The adjoint takes this format as well as F64 and F32
+ * (it differentiates the map of the populations X, decoded to float64). */
 enum dvbm_storage { DVBM_F64 = 0, DVBM_F32 = 1, DVBM_BF16_DEV = 2, DVBM_FP16_DEV = 3, DVBM_F32_DEV = 4 };
 /* Boundaries: periodic; zero-gradient (two ghost layers copy the nearest
  * interior cell); DVBM_WALL (bc_y only): no-slip walls on the faces below row
@@ -194,8 +195,8 @@ int dvbm_set_state_index(dvbm_handle* h, int index);
  * Discrete adjoint (reverse-mode derivative of the update above; it is not
  * part of the paper and follows the discretise-then-differentiate rule: the
  * limiter is differentiated on the branch the forward step takes, and dt is
- * held fixed).  Supported for DVBM_F64 and DVBM_F32 storage (EINVAL
- * otherwise); the arithmetic is float64.  Cotangents lam are dense device
+ * held fixed).  Supported for DVBM_F64, DVBM_F32 and DVBM_F32_DEV storage
+ * (EINVAL otherwise); the arithmetic is float64.  Cotangents lam are dense device
  * float64 arrays lam[2][Q][ny][nx] of dvbm_adjoint_bytes() bytes.
  */
 size_t dvbm_adjoint_bytes(const dvbm_params* p);
@@ -240,7 +241,7 @@ int dvbm_adjoint_step_f32(dvbm_handle* h, const void* state_n, const float* lam_
  * streams, other threads, other handles) race and give wrong results;
  * consecutive calls are safe (each clears the counter it needs).  Other
  * arguments, errors and ordering as for dvbm_adjoint_step (float64
- * cotangents, f64 and f32 storage).  Asynchronous. */
+ * cotangents; f64, f32 and f32_dev storage).  Asynchronous. */
 int dvbm_adjoint_step_noalloc(dvbm_handle* h, const void* state_n, const double* lam_np1, double* lam_n,
                               double* dparams);
 
@@ -257,6 +258,29 @@ int dvbm_adjoint_moments(dvbm_handle* h, const void* state, const double* d_rho,
 int dvbm_adjoint_init(dvbm_handle* h, const double* lam0, const double* rho, const double* ux,
                       const double* uy, const double* T, double* d_rho, double* d_ux, double* d_uy,
                       double* d_T);
+
+/* Limiter branches of the step from state (a device buffer in the
+ * population layout, float64 storage only; EINVAL otherwise or with walls),
+ * for derivative checks: central differences X(p + h) - X(p - h) measure
+ * the derivative only while both runs take the same branch of the limiter
+ * phi (Sec. III A 2) at every face.  For every face the step reconstructs
+ * (the face above each cell along each axis with a non-zero velocity
+ * component, from its upwind side), branch 0 (r <= 0), 1 (beta r),
+ * 2 ((1 + r)/2) or 3 (beta) is mixed with the face's index by the SplitMix64
+ * output function, and the sum of these terms modulo 2^64 is ADDED to the
+ * device uint64 *sig (the caller zeroes it).  Equal branch patterns give
+ * equal sums; a different pattern differs except for a 2^-64 collision.
+ * Asynchronous. */
+int dvbm_limiter_signature(dvbm_handle* h, const void* state, uint64_t* sig);
+
+/* Streaming probe (not part of the method): plain grid-stride kernels that
+ * bound the HBM bandwidth any kernel reaches on this GPU.  mode 0 copies
+ * bytes from src to dst, 1 reads src (dst receives at most one element),
+ * 2 writes dst (src unused, may be NULL); mode + 4 makes the accesses
+ * non-temporal; width 16 or 4 is the bytes each lane moves per access.  src and dst are caller-owned device buffers of
+ * `bytes` bytes (a positive multiple of width, both aligned to width);
+ * stream is a hipStream_t.  EINVAL on a bad argument.  Asynchronous. */
+int dvbm_stream_probe(const void* src, void* dst, size_t bytes, int32_t mode, int32_t width, void* stream);
 
 /* Release the handle (host memory only).  NULL is ignored. */
 void dvbm_destroy(dvbm_handle* h);

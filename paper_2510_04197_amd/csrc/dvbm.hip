@@ -109,17 +109,17 @@ __global__ __launch_bounds__(TILE_TX* TILE_TY) void k_collide_advect_lds(const t
 }
 
 // Row range j of kseg in a column of ny rows for the column sweep: ranges of
-// 3 m rows (m >= 1, 3 m <= ny) from the top; the last one is moved up so
-// that it ends at row ny and may overlap its predecessor (rows computed by
-// both ranges get identical values).  Requires ny >= 3 and
-// kseg = sweep_count(ny, ...).
-__host__ __device__ inline int sweep_len(int ny, int want) {
-  int len = 3 * ((ny + 3 * want - 1) / (3 * want));
-  const int cap = 3 * (ny / 3);
+// u m rows (m >= 1, u m <= ny; u is the ring size of the sweep) from the
+// top; the last one is moved up so that it ends at row ny and may overlap its
+// predecessor (rows computed by both ranges get identical values).
+// Requires ny >= u and kseg = the count sweep_ranges returns.
+__host__ __device__ inline int sweep_len(int ny, int want, int u) {
+  int len = u * ((ny + u * want - 1) / (u * want));
+  const int cap = u * (ny / u);
   return len < cap ? len : cap;
 }
-__device__ inline void sweep_range(int ny, int kseg, int j, int& ya, int& yb) {
-  const int len = sweep_len(ny, kseg);
+__device__ inline void sweep_range(int ny, int kseg, int j, int u, int& ya, int& yb) {
+  const int len = sweep_len(ny, kseg, u);
   ya = j * len;
   if (ya > ny - len) ya = ny - len;
   yb = ya + len;
@@ -153,11 +153,20 @@ template <class S>
 constexpr int sweep_wpe() {
   return sizeof(typename S::T) == 8 ? DVBM_SWEEP_WPE64 : DVBM_SWEEP_WPE;
 }
+#ifndef DVBM_SWEEP_RING64
+#define DVBM_SWEEP_RING64 DVBM_SWEEP_RING
+#endif
+// rows per plane in the sweep's register ring (the row ranges are multiples of it)
+template <class S>
+constexpr int sweep_ring() {
+  return sizeof(typename S::T) == 8 ? DVBM_SWEEP_RING64 : DVBM_SWEEP_RING;
+}
 template <int SPLIT, class S, int BCX, int BCY, int PRM>
 __global__ __launch_bounds__(128 * sweep_k<S>()) __attribute__((amdgpu_waves_per_eu(sweep_wpe<S>()))) void
 k_collide_advect_sweep(const typename S::T* __restrict__ src, typename S::T* __restrict__ dst, KParams kp,
                        int ngroups, int kseg) {
   constexpr int SWEEP_K = sweep_k<S>();
+  constexpr int RING = sweep_ring<S>();
   __shared__ SweepShared sh[SWEEP_K];
   const int total = ngroups * kseg;
   const int per = (total + 7) / 8;
@@ -165,13 +174,13 @@ k_collide_advect_sweep(const typename S::T* __restrict__ src, typename S::T* __r
   if (L >= total) return;
   const int j = L / ngroups, sg = L % ngroups;
   int ya, yb;
-  sweep_range(kp.ny, kseg, j, ya, yb);
+  sweep_range(kp.ny, kseg, j, RING, ya, yb);
   const int w = int(threadIdx.x) / 64, k = w % SWEEP_K;
   const int x0 = (sg * SWEEP_K + k) * SWEEP_OWN;  // may lie beyond nx: then the wave stores nothing
   if (w < SWEEP_K)
-    sweep_update<SPLIT, S, BCX, BCY, PRM, 0>(src, dst, kp, x0, ya, yb, sh[k]);
+    sweep_update<SPLIT, S, BCX, BCY, PRM, 0, RING>(src, dst, kp, x0, ya, yb, sh[k]);
   else
-    sweep_update<SPLIT, S, BCX, BCY, PRM, 1>(src, dst, kp, x0, ya, yb, sh[k]);
+    sweep_update<SPLIT, S, BCX, BCY, PRM, 1, RING>(src, dst, kp, x0, ya, yb, sh[k]);
 }
 
 // ------------------------------------------------------------ equilibrium initialisation
@@ -513,6 +522,111 @@ __global__ __launch_bounds__(256) void k_adjoint_init(const double* __restrict__
   }
 }
 
+// ------------------------------------------------------------ limiter branches (derivative checks)
+// SplitMix64 output function (Steele, Lea & Flood, OOPSLA 2014): a bijective
+// 64-bit mix, so distinct (face, branch) keys give independent-looking terms.
+__device__ inline unsigned long long mix64(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Branch of the limiter function phi(r) = max(0, min(beta r, (1 + r)/2, beta))
+// (Sec. III A 2) in L(a, b) = (b/2) phi(a/b): 0 when r <= 0 (a b <= 0),
+// 1 for beta r, 2 for (1 + r)/2, 3 for beta, the smallest of the three
+// taken in that order on ties.
+__device__ inline int limiter_branch(double a, double b, double beta) {
+  if (!(a * b > 0.0)) return 0;
+  const double A = beta * fabs(a), M = 0.5 * fabs(a + b), B = beta * fabs(b);
+  return (A <= M && A <= B) ? 1 : (M <= B ? 2 : 3);
+}
+
+// Signature of the limiter branches of one step from float64 populations X
+// (dense planes with row pitch kp.pitch): for every population plane with a
+// non-zero velocity component along an axis, the face above each cell along
+// that axis is reconstructed from its upwind side (v > 0: cells c-1, c, c+1;
+// v < 0: c, c+1, c+2), and sig receives the sum, over those faces, of
+// mix64(4 face + branch).  Steps that take the same branch at every face
+// give equal sums; a step with any face on another branch gives a different
+// sum unless the 64-bit sums collide.
+template <int SPLIT, int BCX, int BCY>
+__global__ __launch_bounds__(256) void k_limiter_signature(const double* __restrict__ X, KParams kp,
+                                                           unsigned long long* sig) {
+  constexpr int N1 = Set<SPLIT>::N1;
+  constexpr int Q = Set<SPLIT>::Q;
+  using L = GH<N1>;
+  const int64_t n = int64_t(kp.nx) * kp.ny;
+  const double beta = 0.5 * kp.beta2;
+  unsigned long long acc = 0ull;
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x) {
+    const int y = int(k / kp.nx), x = int(k % kp.nx);
+    for (int pl = 0; pl < 2 * Q; ++pl) {
+      const double* P = X + int64_t(pl) * kp.plane;
+      const int i = pl % Q;
+      for (int ax = 0; ax < 2; ++ax) {
+        const double v = ax == 0 ? L::xi(i / N1) : L::xi(i % N1);
+        if (v == 0.0) continue;
+        auto at = [&](int d) -> double {
+          if (ax == 0) return P[int64_t(y) * kp.pitch + wrap_any<BCX>(x + d, kp.nx)];
+          return P[int64_t(wrap_any<BCY>(y + d, kp.ny)) * kp.pitch + x];
+        };
+        const double a = v > 0.0 ? at(0) - at(-1) : at(1) - at(2);
+        const double b = v > 0.0 ? at(1) - at(0) : at(0) - at(1);
+        const unsigned long long face = (unsigned long long)((int64_t(ax) * 2 * Q + pl) * n + k);
+        acc += mix64(4ull * face + unsigned(limiter_branch(a, b, beta)));
+      }
+    }
+  }
+  __shared__ unsigned long long sh[256];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (int(threadIdx.x) < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(sig, sh[0]);  // a sum modulo 2^64: order-independent
+}
+
+// ------------------------------------------------------------ streaming probe
+// Plain grid-stride streams over n elements of V (16 bytes: four uint32, or
+// 4 bytes: one uint32): mode 0 copies src to dst, 1 reads src (the xor of what
+// a thread read is stored only if it equals a value no input here holds, so
+// the loads stay), 2 writes dst; NT marks the accesses non-temporal.  They
+// bound the HBM bandwidth a kernel reaches on this GPU with accesses of that
+// width.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ inline bool is_marker(u32x4 a) { return a.x == 0x9e3779b9u && a.y == 0x7f4a7c15u && a.z == 1u && a.w == 2u; }
+__device__ inline bool is_marker(uint32_t a) { return a == 0x9e3779b9u; }
+template <class V, bool NT>
+__device__ inline V ld_stream(const V* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <class V, bool NT>
+__device__ inline void st_stream(V* p, V v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+template <class V, bool NT>
+__global__ __launch_bounds__(256) void k_stream(const V* __restrict__ src, V* __restrict__ dst, int64_t n, int mode) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (mode == 0) {
+#pragma unroll 4
+    for (; i < n; i += stride) st_stream<V, NT>(dst + i, ld_stream<V, NT>(src + i));
+  } else if (mode == 1) {
+    V acc = V(0u);
+#pragma unroll 4
+    for (; i < n; i += stride) acc ^= ld_stream<V, NT>(src + i);
+    if (is_marker(acc)) dst[0] = acc;
+  } else {
+    const V v = V(0u);
+#pragma unroll 4
+    for (; i < n; i += stride) st_stream<V, NT>(dst + i, v);
+  }
+}
+
 }  // namespace dvbm
 
 // =================================================================== C ABI
@@ -624,6 +738,15 @@ KParams make_kparams(const dvbm_params& p, double dt) {
   return k;
 }
 
+#ifndef DVBM_SWEEP_ROUNDS64
+#define DVBM_SWEEP_ROUNDS64 6
+#endif
+#ifndef DVBM_SWEEP_ROUNDS32
+#define DVBM_SWEEP_ROUNDS32 4
+#endif
+#ifndef DVBM_SWEEP_ROUNDS16
+#define DVBM_SWEEP_ROUNDS16 1
+#endif
 // Row ranges per strip group for the column sweep.  One workgroup fits a
 // CU at a time, so one round of ranges (as many workgroups as the device
 // holds) ends with its slowest CU; `rounds` rounds of shorter ranges let the
@@ -632,7 +755,7 @@ KParams make_kparams(const dvbm_params& p, double dt) {
 // round nor ranges shorter than 9 rows.  Measured on the 4096^2 thermal
 // wave: float64 storage gains 15 % at 6 rounds, float32 4.5 % at 4 rounds,
 // the 16-bit formats nothing.
-int sweep_ranges(const void* kern, int block, int ngroups, int ny, int rounds) {
+int sweep_ranges(const void* kern, int block, int ngroups, int ny, int rounds, int unit) {
   int dev = 0, ncu = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -644,10 +767,10 @@ int sweep_ranges(const void* kern, int block, int ngroups, int ny, int rounds) {
   const int one = ncu * per_cu / ngroups;  // ranges per strip group in one round
   int want = rounds * one < ny / 48 ? rounds * one : ny / 48;
   if (want < one) want = one;
-  if (want > ny / 9) want = ny / 9;
+  if (want > ny / (3 * unit)) want = ny / (3 * unit);
   if (want < 1) want = 1;
   // the number of ranges of sweep_len rows that cover the column
-  const int len = sweep_len(ny, want);
+  const int len = sweep_len(ny, want, unit);
   return (ny + len - 1) / len;
 }
 
@@ -697,8 +820,11 @@ void launch_step_pr(const dvbm_handle* h, const void* src, void* dst) {
       const auto kern = k_collide_advect_sweep<SPLIT, S, BCX, BCY, PRM>;
       const int nstrips = (h->p.nx + SWEEP_OWN - 1) / SWEEP_OWN;
       const int ngroups = (nstrips + SWEEP_K - 1) / SWEEP_K;
-      if (h->sweep_kseg == 0) h->sweep_kseg = sweep_ranges(reinterpret_cast<const void*>(kern), 128 * SWEEP_K, ngroups, h->p.ny,
-                                     sizeof(T) == 8 ? 6 : (sizeof(T) == 4 ? 4 : 1));
+      if (h->sweep_kseg == 0)
+        h->sweep_kseg = sweep_ranges(reinterpret_cast<const void*>(kern), 128 * SWEEP_K, ngroups, h->p.ny,
+                                     sizeof(T) == 8 ? DVBM_SWEEP_ROUNDS64
+                                                    : (sizeof(T) == 4 ? DVBM_SWEEP_ROUNDS32 : DVBM_SWEEP_ROUNDS16),
+                                     sweep_ring<S>());
       const int total = ngroups * h->sweep_kseg;
       const dim3 grid(8 * ((total + 7) / 8));
       hipLaunchKernelGGL(kern, grid, dim3(128 * SWEEP_K), 0, h->stream, s, d, h->kp, ngroups, h->sweep_kseg);
@@ -796,9 +922,10 @@ void adjoint_bc(const dvbm_handle* h, const void* state, const LT* lam1, LT* lam
 }  // namespace dvbm_launch
 
 #if defined(DVBM_PART)
-// kernel unit DVBM_PART = 5 (split - 1) + storage + 1
+// kernel unit DVBM_PART = 5 (split - 1) + storage + 1; the adjoint takes the
+// float64, float32 and float32-deviation storages (storage 0, 1, 4)
 template void dvbm_launch::step<(DVBM_PART - 1) / 5 + 1, DVBM_PART_STORE>(const dvbm_handle*, const void*, void*);
-#if (DVBM_PART - 1) % 5 < 2
+#if (DVBM_PART - 1) % 5 < 2 || (DVBM_PART - 1) % 5 == 4
 template void dvbm_launch::adjoint<(DVBM_PART - 1) / 5 + 1, DVBM_PART_STORE, double>(
     const dvbm_handle*, const void*, const double*, double*, double*, double*, double*);
 template void dvbm_launch::adjoint<(DVBM_PART - 1) / 5 + 1, DVBM_PART_STORE, float>(
@@ -824,8 +951,10 @@ DVBM_EXTERN_STEP(2, StoreF16)
 DVBM_EXTERN_STEP(2, StoreF32Dev)
 DVBM_EXTERN_ADJ(1, StoreF64)
 DVBM_EXTERN_ADJ(1, StoreF32)
+DVBM_EXTERN_ADJ(1, StoreF32Dev)
 DVBM_EXTERN_ADJ(2, StoreF64)
 DVBM_EXTERN_ADJ(2, StoreF32)
+DVBM_EXTERN_ADJ(2, StoreF32Dev)
 
 // ------------------------------------------------------------ fixed scratch
 // Device memory of dvbm_adjoint_step_noalloc, for callers that cannot
@@ -950,17 +1079,22 @@ struct ReadoutAdjointOp {
   }
 };
 
-// The adjoint entry points support the float64 and float32 storages.
+// The adjoint entry points support the float64, float32 and float32-deviation
+// storages (adjoint_storage_ok rejects the others before dispatch).
 template <template <int, class> class F, class... A>
 void dispatch_adjoint(const dvbm_params& p, A&&... args) {
   if (p.split == 2) {
     if (p.storage == DVBM_F64)
       F<2, StoreF64>::run(args...);
+    else if (p.storage == DVBM_F32_DEV)
+      F<2, StoreF32Dev>::run(args...);
     else
       F<2, StoreF32>::run(args...);
   } else {
     if (p.storage == DVBM_F64)
       F<1, StoreF64>::run(args...);
+    else if (p.storage == DVBM_F32_DEV)
+      F<1, StoreF32Dev>::run(args...);
     else
       F<1, StoreF32>::run(args...);
   }
@@ -1174,8 +1308,8 @@ size_t dvbm_adjoint_bytes(const dvbm_params* p) {
 }
 
 static int adjoint_storage_ok(const dvbm_handle* h, const char* who) {
-  if (h->p.storage != DVBM_F64 && h->p.storage != DVBM_F32)
-    return fail(DVBM_EINVAL, std::string(who) + ": the adjoint supports f64 and f32 storage");
+  if (h->p.storage != DVBM_F64 && h->p.storage != DVBM_F32 && h->p.storage != DVBM_F32_DEV)
+    return fail(DVBM_EINVAL, std::string(who) + ": the adjoint supports f64, f32 and f32_dev storage");
   if (h->p.bc_y == DVBM_WALL) return fail(DVBM_EINVAL, std::string(who) + ": the adjoint does not support walls");
   // the flux adjoint stores each cotangent plane through one buffer resource
   // with 32-bit offsets and discards stores at offset 2^31 (the distribution
@@ -1239,6 +1373,61 @@ int dvbm_adjoint_moments(dvbm_handle* h, const void* state, const double* d_rho,
   if (!h || !state || !lam) return fail(DVBM_EINVAL, "dvbm_adjoint_moments: NULL argument");
   if (int rc = adjoint_storage_ok(h, "dvbm_adjoint_moments")) return rc;
   dispatch_adjoint<ReadoutAdjointOp>(h->p, h, state, d_rho, d_ux, d_uy, d_T, lam);
+  HIP_TRY(hipGetLastError());
+  return DVBM_OK;
+}
+
+int dvbm_stream_probe(const void* src, void* dst, size_t bytes, int32_t mode, int32_t width, void* stream) {
+  const int m = mode & 3;
+  const bool nt = (mode & 4) != 0;
+  if (mode < 0 || mode > 6 || m > 2 || (width != 16 && width != 4) || bytes < size_t(width) ||
+      bytes % size_t(width))
+    return fail(DVBM_EINVAL,
+                "dvbm_stream_probe: mode 0..2 (+4 non-temporal), width 16 or 4, bytes a positive multiple of width");
+  if ((m != 2 && !src) || !dst) return fail(DVBM_EINVAL, "dvbm_stream_probe: NULL buffer");
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % size_t(width))
+    return fail(DVBM_EINVAL, "dvbm_stream_probe: buffers must be aligned to width");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n = int64_t(bytes / size_t(width));
+  // about four elements per thread (measured fastest for 4 GiB; fewer, longer-running blocks lose up to 20 %)
+  const int64_t want = (n + 4 * 256 - 1) / (4 * 256);
+  const dim3 grid(unsigned(want < (int64_t(1) << 20) ? want : (int64_t(1) << 20))), block(256);
+  auto launch = [&](auto kern, auto* sp, auto* dp) { hipLaunchKernelGGL(kern, grid, block, 0, s, sp, dp, n, m); };
+  if (width == 16) {
+    const auto* sp = static_cast<const u32x4*>(src);
+    auto* dp = static_cast<u32x4*>(dst);
+    if (nt) launch(k_stream<u32x4, true>, sp, dp);
+    else launch(k_stream<u32x4, false>, sp, dp);
+  } else {
+    const auto* sp = static_cast<const uint32_t*>(src);
+    auto* dp = static_cast<uint32_t*>(dst);
+    if (nt) launch(k_stream<uint32_t, true>, sp, dp);
+    else launch(k_stream<uint32_t, false>, sp, dp);
+  }
+  HIP_TRY(hipGetLastError());
+  return DVBM_OK;
+}
+
+int dvbm_limiter_signature(dvbm_handle* h, const void* state, uint64_t* sig) {
+  if (!h || !state || !sig) return fail(DVBM_EINVAL, "dvbm_limiter_signature: NULL argument");
+  if (h->p.storage != DVBM_F64) return fail(DVBM_EINVAL, "dvbm_limiter_signature: float64 storage only");
+  if (h->p.bc_y == DVBM_WALL) return fail(DVBM_EINVAL, "dvbm_limiter_signature: walls are not supported");
+  const double* X = static_cast<const double*>(state);
+  auto* out = reinterpret_cast<unsigned long long*>(sig);
+  const bool px = h->p.bc_x == DVBM_PERIODIC, py = h->p.bc_y == DVBM_PERIODIC;
+  const dim3 grid(RED_BLOCKS), block(256);
+  auto launch = [&](auto kern) { hipLaunchKernelGGL(kern, grid, block, 0, h->stream, X, h->kp, out); };
+  if (h->p.split == 2) {
+    if (px && py) launch(k_limiter_signature<2, BC_PERIODIC, BC_PERIODIC>);
+    else if (py) launch(k_limiter_signature<2, BC_ZERO_GRADIENT, BC_PERIODIC>);
+    else if (px) launch(k_limiter_signature<2, BC_PERIODIC, BC_ZERO_GRADIENT>);
+    else launch(k_limiter_signature<2, BC_ZERO_GRADIENT, BC_ZERO_GRADIENT>);
+  } else {
+    if (px && py) launch(k_limiter_signature<1, BC_PERIODIC, BC_PERIODIC>);
+    else if (py) launch(k_limiter_signature<1, BC_ZERO_GRADIENT, BC_PERIODIC>);
+    else if (px) launch(k_limiter_signature<1, BC_PERIODIC, BC_ZERO_GRADIENT>);
+    else launch(k_limiter_signature<1, BC_ZERO_GRADIENT, BC_ZERO_GRADIENT>);
+  }
   HIP_TRY(hipGetLastError());
   return DVBM_OK;
 }

@@ -200,8 +200,15 @@ struct SweepShared {
 #endif
 constexpr int SWEEP_K = DVBM_SWEEP_K;
 
+// Rows held per plane by the column sweep: the three rows of the stencil
+// window plus RING - 3 rows in flight, so a row is requested RING - 2 rows
+// before the row step that first reads it.
+#ifndef DVBM_SWEEP_RING
+#define DVBM_SWEEP_RING 3
+#endif
+
 // Rows [ya, yb) of the strip whose first owned column is x0, distribution D
-// (0: f, 1: g); yb - ya is a positive multiple of 3.  The other
+// (0: f, 1: g); yb - ya is a positive multiple of RING.  The other
 // distribution of the strip is advanced by the other wave of the workgroup,
 // which shares the moments through sh.
 //
@@ -210,14 +217,17 @@ constexpr int SWEEP_K = DVBM_SWEEP_K;
 // its neighbour reads it by a lane shift; in y the value of the face below
 // row y is carried over from row y - 1.  Window of plane i (y-node xi_b):
 // rows y-1 .. y+1 when xi_b > 0, y .. y+2 when xi_b < 0 (upwind side
-// first), rows y .. y+2 when xi_b = 0 (loaded early, since the row's
-// moments need it first).  A window of three rows lives in three registers
-// whose roles rotate from row to row, so the row loop is unrolled three
-// times and a row's load lands directly in the register that the window
-// drops.
-template <int SPLIT, class S, int BCX, int BCY, int PRM, int D>
+// first), row y when xi_b = 0.  The window and the rows in flight behind it
+// live in a ring of RING registers per plane whose roles rotate from row to
+// row, so the row loop is unrolled RING times and a row's load lands
+// directly in the register that the window drops: the row after the ring's
+// last one (y + RING - 1 when xi_b > 0, y + RING otherwise).  The moments at
+// the start of a row read every plane, so each load has RING - 2 row steps
+// of the whole workgroup to arrive.
+template <int SPLIT, class S, int BCX, int BCY, int PRM, int D, int RING>
 __device__ inline void sweep_update(const typename S::T* __restrict__ src, typename S::T* __restrict__ dst,
                                     const KParams& kp, int x0, int ya, int yb, SweepShared& sh) {
+  static_assert(RING >= 3 && RING <= 4, "three window rows, at most four in all (grids have ny >= 4)");
   using R = typename S::C;
   using T = typename S::T;
   constexpr int N1 = Set<SPLIT>::N1;
@@ -246,8 +256,8 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
   const R kx = R(kp.kx), ky = R(kp.ky);
   auto row = [&](int yy) -> uint32_t { return uint32_t(wrap<BCY>(yy, ny)) * row_bytes; };
   // stored bit pattern of plane i at row offset roff; Bits<T>::decode gives the stored value
-  auto load = [&](int i, uint32_t roff) -> R {
-    return Bits<T>::keep(Buf<T>::ld(rsrc_src, uint32_t(i) * plane_bytes + roff, vo));
+  auto load = [&](int i, uint32_t roff, uint32_t lo) -> R {
+    return Bits<T>::keep(Buf<T>::ld(rsrc_src, uint32_t(i) * plane_bytes + roff, lo));
   };
   // face value between c and n, upwind cell c, far-side cell u: c + L(c - u, n - c) / 4
   auto face = [&](R u, R c, R n) -> R { return c + R(0.25) * lim4(c - u, n - c, beta2); };
@@ -265,38 +275,31 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
   // the rest value r_i is the same for every population of f, and of g in split II
   constexpr bool rest_uniform = D == 0 || SPLIT == 2;
 
-  // win[i][(P + r) % 3] holds window row r at phase P = (y - ya) % 3; a
-  // row enters the window as its bit pattern and is decoded in place at its
-  // first use (y-moving planes: the face above the row two rows earlier;
-  // xi_b = 0: as the row's own value)
-  R win[Q][3];
+  // win[i][(P + r) % RING] holds ring row r at phase P = (y - ya) % RING:
+  // row y - 1 + r when xi_b > 0, y + r otherwise.  A row enters the ring as
+  // its bit pattern and is decoded in place at its first use (y-moving
+  // planes: the face above the row two rows earlier; xi_b = 0: as the row's
+  // own value)
+  R win[Q][RING];
   R fbelow[Q];  // face value below the current row (planes with xi_b != 0)
   {
-    // warm-up, issued in the order of first use: rows y-2 .. y, then the
-    // lead rows of the planes with xi_b < 0 (their groups come first), of
-    // xi_b > 0, and the two rows of xi_b = 0 needed from the next row on
+    // warm-up, issued in the order of first use: rows ya-2 .. ya, then the
+    // stencil rows of the first row step, then the rows in flight
     R extra[Q];
-    constexpr int order[7][2] = {{-2, 0}, {-1, 0}, {0, 0}, {1, -1}, {2, -1}, {1, 1}, {1, 2}};
 #pragma unroll
-    for (int s = 0; s < 7; ++s) {
-      const int dy = order[s][0], side = order[s][1];  // side: sign of xi_b that loads (0: all)
+    for (int dy = -2; dy <= RING - 1; ++dy) {
       const uint32_t ro = row(ya + dy);
       static_for<Q>([&](auto kc) {
         constexpr int i = decltype(kc)::value;
         constexpr double xb = L::xi(i % N1);
-        if (side == 2) {
-          if (xb == 0.0) win[i][2] = load(i, row(ya + 2));
-          return;
-        }
-        if (side != 0 && !((side > 0 && xb > 0.0) || (side < 0 && xb <= 0.0))) return;
         if (xb > 0.0) {
-          if (dy == -2) extra[i] = load(i, ro);
-          else if (dy <= 1) win[i][dy + 1] = load(i, ro);
+          if (dy == -2) extra[i] = load(i, ro, vo);
+          else if (dy <= RING - 2) win[i][dy + 1] = load(i, ro, vo);
         } else if (xb < 0.0) {
-          if (dy == -1) extra[i] = load(i, ro);
-          else if (dy >= 0) win[i][dy] = load(i, ro);
-        } else if (dy >= 0 && dy <= 1) {
-          win[i][dy] = load(i, ro);
+          if (dy == -1) extra[i] = load(i, ro, vo);
+          else if (dy >= 0) win[i][dy] = load(i, ro, vo);
+        } else if (dy >= 0) {
+          win[i][dy] = load(i, ro, vo);
         }
       });
     }
@@ -316,7 +319,14 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
   auto row_step = [&](auto phc, int y) {
     constexpr int P = decltype(phc)::value;
     const uint32_t r_st = uint32_t(y) * row_bytes;
-    const uint32_t r_p2 = row(y + 2), r_p3 = row(y + 3);
+    const uint32_t r_pos = row(y + RING - 1), r_neg = row(y + RING);  // rows entering the ring
+    // a row entering the ring is first read RING - 2 row steps later (its
+    // face), or RING steps later when xi_b = 0 (its own value); near the end
+    // of the range that step lies beyond yb, and the load gets the offset
+    // 2^31, which the bounds check of the buffer resource answers with 0
+    // and no memory access
+    const uint32_t vo_face = y + RING - 2 < yb ? vo : 0x80000000u;
+    const uint32_t vo_own = y + RING < yb ? vo : 0x80000000u;
 
     // the row's populations (stored values), their float64 moments, shared
     R cen[Q];
@@ -324,7 +334,7 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
       constexpr int i = decltype(kc)::value;
       constexpr double xb = L::xi(i % N1);
       if (xb == 0.0) win[i][P] = Bits<T>::decode(win[i][P]);
-      cen[i] = xb > 0.0 ? win[i][(P + 1) % 3] : win[i][P];
+      cen[i] = xb > 0.0 ? win[i][(P + 1) % RING] : win[i][P];
     });
     NodeMoments m;
     {
@@ -405,8 +415,8 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
           div += kx * R(xv) * (lane_next(fl) - fl);
         }
         if (xb != 0.0) {
-          wn[(P + 2) % 3] = Bits<T>::decode(wn[(P + 2) % 3]);
-          const R r0 = wn[P], r1 = wn[(P + 1) % 3], r2 = wn[(P + 2) % 3];
+          wn[(P + 2) % RING] = Bits<T>::decode(wn[(P + 2) % RING]);
+          const R r0 = wn[P], r1 = wn[(P + 1) % RING], r2 = wn[(P + 2) % RING];
           const R fa = xb > 0.0 ? face(r0, r1, r2) : face(r2, r1, r0);  // X_{y+1/2}
           div += ky * R(xb) * (fa - fbelow[i]);
           fbelow[i] = fa;
@@ -422,17 +432,14 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
           Buf<T>::st(plane_rsrc(dst, D * Q + i, plane_bytes), r_st, vo_st, S::enc(xn, R(1), R(0)));
         else
           Buf<T>::st(rsrc_dst, uint32_t(i) * plane_bytes + r_st, vo_st, S::enc(xn, R(1), R(0)));
-        // the window drops its first row; that register receives the row it now needs
-        wn[P] = load(i, xb > 0.0 ? r_p2 : r_p3);
+        // the window drops its first row; that register receives the row after the ring's last
+        wn[P] = load(i, xb > 0.0 ? r_pos : r_neg, xb != 0.0 ? vo_face : vo_own);
       });
     });
   };
 
-  for (int y = ya; y < yb; y += 3) {
-    row_step(std::integral_constant<int, 0>{}, y);
-    row_step(std::integral_constant<int, 1>{}, y + 1);
-    row_step(std::integral_constant<int, 2>{}, y + 2);
-  }
+  for (int y = ya; y < yb; y += RING)
+    static_for<RING>([&](auto pc) { row_step(pc, y + decltype(pc)::value); });
 }
 
 }  // namespace dvbm

@@ -72,6 +72,8 @@ SIGNATURES = {
     "dvbm_adjoint_step_noalloc": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "dvbm_adjoint_moments": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "dvbm_adjoint_init": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "dvbm_limiter_signature": (ctypes.c_int, [_P, _P, _P]),
+    "dvbm_stream_probe": (ctypes.c_int, [_P, _P, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _P]),
     "dvbm_last_error": (ctypes.c_char_p, []),
 }
 
@@ -129,6 +131,15 @@ def make_params(nx, ny, split=2, storage="f32", bc_x="periodic", bc_y="periodic"
     p.wall_T[0], p.wall_T[1] = map(float, wall_T)      # bc_y == "wall": lower, upper wall
     p.wall_ux[0], p.wall_ux[1] = map(float, wall_ux)
     return p
+
+
+def stream_probe(src: torch.Tensor | None, dst: torch.Tensor, nbytes: int, mode: int, width: int,
+                 stream: torch.cuda.Stream):
+    """``dvbm_stream_probe``: plain streaming copy (mode 0), read (1) or write (2) of ``nbytes``;
+    mode + 4 makes the accesses non-temporal."""
+    lib = load_library()
+    _check(lib.dvbm_stream_probe(_ptr(src) if src is not None else None, _ptr(dst), int(nbytes), int(mode),
+                                 int(width), ctypes.c_void_p(stream.cuda_stream)))
 
 
 def velocity_set(split: int, R: float = 1.0, T_ref: float = 1.0):
@@ -279,6 +290,13 @@ class Solver:
                                           *[_ptr(outs[k]) if k in outs else None for k in names]))
         self.stream.synchronize()
         return outs
+
+    def limiter_signature(self, state: torch.Tensor, out: torch.Tensor):
+        """Adds the limiter-branch signature of the step from ``state`` (float64 storage) to the
+        device ``int64`` scalar tensor ``out`` (``dvbm_limiter_signature``; a sum modulo 2^64)."""
+        if out.dtype != torch.int64 or out.numel() != 1 or out.device.type != self.device.type:
+            raise TypeError("out must be a one-element int64 device tensor")
+        _check(self.lib.dvbm_limiter_signature(self._h(), _ptr(state), _ptr(out)))
 
     def close(self):
         if getattr(self, "handle", None):

@@ -134,3 +134,26 @@ def test_step_kernel_name_follows_the_auto_rule():
     assert bench.step_kernel_name("f32", small) == "k_collide_advect"
     assert bench.step_kernel_name("f32", huge) == "k_collide_advect"  # distribution above 2 GiB
     assert bench.step_kernel_name("bf16_dev", huge) == "k_collide_advect_sweep"
+
+
+def test_stream_probe_rejects_bad_arguments_on_the_host():
+    """dvbm_stream_probe validates mode, width, size, pointers and alignment
+    before any launch (EINVAL, no GPU needed)."""
+    from paper_2510_04197_amd import dvbm
+    lib = dvbm.load_library()
+    buf = ctypes.c_void_p(4096)  # never dereferenced: every call below fails its checks first
+    for mode, width, nbytes in ((3, 16, 64), (7, 16, 64), (-1, 16, 64), (0, 8, 64), (0, 16, 0), (0, 16, 24),
+                                (0, 4, 6)):
+        assert lib.dvbm_stream_probe(buf, buf, nbytes, mode, width, None) == dvbm.DVBM_EINVAL
+    assert lib.dvbm_stream_probe(None, buf, 64, 0, 16, None) == dvbm.DVBM_EINVAL
+    assert lib.dvbm_stream_probe(buf, None, 64, 2, 16, None) == dvbm.DVBM_EINVAL
+    assert lib.dvbm_stream_probe(ctypes.c_void_p(4100), buf, 64, 0, 16, None) == dvbm.DVBM_EINVAL
+    assert b"dvbm_stream_probe" in lib.dvbm_last_error()
+
+
+def test_new_entry_points_reject_null_handles():
+    from paper_2510_04197_amd import dvbm
+    lib = dvbm.load_library()
+    p = ctypes.c_void_p(4096)
+    assert lib.dvbm_limiter_signature(None, p, p) == dvbm.DVBM_EINVAL
+    assert lib.dvbm_adjoint_step_noalloc(None, p, p, p, None) == dvbm.DVBM_EINVAL
