@@ -324,25 +324,45 @@ def sampled_check(s: Solver, p, nsamples=96, seed=0):
     return got, torch.stack([fo, go]), win[:, :, :, 2, 2]
 
 
-@pytest.mark.parametrize("storage,tol", (("f32", 1e-5), ("f64", 1e-12)))
+# One float32 step from a stored state: the oracle updates the same (float32)
+# state in float64, so the GPU's result differs by the float32 rounding of one
+# update only.  A step moves these states by about 1e-6 relative, so the state
+# tolerance of 1e-5 alone could not see an error in the float32 update; the
+# bound of 16 float32 ulps (2^-24 relative) can.
+F32_STEP = 16 * 2.0 ** -24
+
+
+def check_sampled(got, ref, before, storage, tol, what):
+    e = rel(got, ref)
+    print(f"[{what}] {storage}: relative L2 against the oracle {e:.2e}, increment {rel(got - before, ref - before):.2e}",
+          flush=True)
+    assert e < tol
+    if storage == "f64":
+        assert rel(got - before, ref - before) < 1e-9
+    else:
+        assert e < F32_STEP
+
+
+@pytest.mark.parametrize("storage,tol", (("f32", 1e-5), ("f64", 1e-12), ("f32_dev", 1e-5)))
 def test_vortex_1024_sampled(storage, tol):
     wl = isentropic_vortex(1024, seed=0, mach_adv=1.0, mach_v=0.3, r_frac=0.05)
     s, p = solver(wl, split=2, storage=storage, Pr=0.71, tau_ref=5e-5)
     s.step(2)
     got, ref, before = sampled_check(s, p)
-    assert rel(got, ref) < tol
-    if storage == "f64":
-        assert rel(got - before, ref - before) < 1e-9
+    check_sampled(got, ref, before, storage, tol, "vortex 1024")
 
 
-@pytest.mark.parametrize("Pr,gamma", ((0.1, 1.4), (2.0, 5.0 / 3.0)))
-def test_shock_vortex_2048x1024_sampled(Pr, gamma):
+@pytest.mark.parametrize("storage", ("f32", "f32_dev"))
+@pytest.mark.parametrize("Pr,gamma", [(Pr, g) for Pr in (0.1, 0.71, 2.0) for g in (1.4, 5.0 / 3.0)])
+def test_shock_vortex_2048x1024_sampled(Pr, gamma, storage):
+    """The six (Pr, gamma) pairs of the 2048 x 1024 shock-vortex workload, x
+    zero-gradient, y periodic: sampled cells of a step against the oracle."""
     wl = shock_vortex(2048, 1024, mach_s=1.2, mach_v=0.25, r_frac=0.075, gamma=gamma)
-    s, p = solver(wl, split=2, storage="f32", Pr=Pr, gamma=gamma, tau_ref=wl.phys["mu"], bc_x="zero_gradient",
+    s, p = solver(wl, split=2, storage=storage, Pr=Pr, gamma=gamma, tau_ref=wl.phys["mu"], bc_x="zero_gradient",
                   bc_y="periodic")
     s.step(2)
-    got, ref, _ = sampled_check(s, p)
-    assert rel(got, ref) < 1e-5
+    got, ref, before = sampled_check(s, p)
+    check_sampled(got, ref, before, storage, 1e-5, f"shock-vortex Pr {Pr} gamma {gamma:.3f}")
 
 
 @pytest.mark.parametrize("storage,tol", (("f32", 1e-5), ("f64", 1e-12), ("f32_dev", 1e-5)))
@@ -350,8 +370,8 @@ def test_thermal_wave_4096_sampled(storage, tol):
     wl = thermal_wave(4096, seed=0)
     s, p = solver(wl, split=2, storage=storage, Pr=0.5, tau_ref=5e-5)
     s.step(1)
-    got, ref, _ = sampled_check(s, p, nsamples=64)
-    assert rel(got, ref) < tol
+    got, ref, before = sampled_check(s, p, nsamples=64)
+    check_sampled(got, ref, before, storage, tol, "thermal wave 4096")
 
 
 def test_largest_grids_sampled():
@@ -588,24 +608,78 @@ def test_vortex_1024_fp32_vs_fp64(nsteps):
             assert full < 1e-5 and down < 1e-5, (st, k)
 
 
+@pytest.mark.parametrize("Pr,gamma", [(Pr, g) for Pr in (0.1, 0.71, 2.0) for g in (1.4, 5.0 / 3.0)])
+def test_shock_vortex_2048x1024_fp32_vs_fp64_8000_steps(Pr, gamma):
+    """The 2048 x 1024 shock-vortex workload over its 8000 steps, each (Pr,
+    gamma) pair: both float32 storages against the float64-storage run (itself
+    checked against the oracle on sampled cells), relative L2 of rho and T.
+    Measured: f32 rho 6.9e-6 to 1.0e-5, T 1.06e-5 to 2.0e-5; f32_dev rho 7.5e-6
+    to 9.5e-6, T 1.04e-5 to 1.37e-5 (8 x 8 block averages within 8 % of these).
+    Density meets 1e-5; temperature, the difference of the total and the
+    kinetic energy in this Mach 1.2 flow, does not: deviations from the rest
+    state are as large as the values here, so f32_dev gains little.  The
+    bounds (rho 1.5e-5, T 3e-5 and 2e-5) hold what was measured."""
+    wl = shock_vortex(2048, 1024, mach_s=1.2, mach_v=0.25, r_frac=0.075, gamma=gamma)
+    out = {}
+    for storage in ("f64", "f32", "f32_dev"):
+        s, _ = solver(wl, split=2, storage=storage, Pr=Pr, gamma=gamma, tau_ref=wl.phys["mu"],
+                      bc_x="zero_gradient", bc_y="periodic")
+        s.step(8000)
+        m = s.moments(fields=True)
+        assert np.isfinite(m["sums"]).all()
+        out[storage] = {k: m[k] for k in ("rho", "T")}
+        s.close()
+    errs = {(st, k): rel(out[st][k], out["f64"][k]) for st in ("f32", "f32_dev") for k in ("rho", "T")}
+    print(f"[shock-vortex 2048x1024] Pr {Pr} gamma {gamma:.3f}, 8000 steps: "
+          + ", ".join(f"{st} {k} {v:.2e}" for (st, k), v in errs.items()), flush=True)
+    assert errs["f32", "rho"] < 1.5e-5 and errs["f32_dev", "rho"] < 1.5e-5
+    assert errs["f32", "T"] < 3e-5 and errs["f32_dev", "T"] < 2e-5
+
+
 def test_thermal_wave_4096_precision_2000_steps():
     """The 4096^2 thermal wave over 2000 steps (CFL 0.01, dt / tau = 0.04):
     a step moves a population by a few float32 ulps in all, so float32 values
     drift from the float64-storage run by 2e-5 (relative L2, growing with the
     step count), while float32 deviations from the rest state, a twentieth of
     the values' size here, stay within 1e-5, in the column sweep and in the
-    per-cell kernel alike."""
+    per-cell kernel alike.
+
+    Conductivity from the same runs: over 4e-3 time units (0.5 % of the
+    acoustic time L / c) the density does not move, so the wave's mode decays
+    at the isochoric diffusivity kappa / (rho c_v) = gamma nu / Pr, less the
+    start-up of the heat flux from the initial equilibrium (about tau_alpha =
+    mu / (p Pr)): rate = gamma (nu / Pr)(1 - tau_alpha / t).  The float64 run
+    gives it within 1e-3 (measured 5e-4), float32 deviations within 3 %
+    (measured 1.5 %); float32 values, whose drift is of the size of the
+    2e-5 decay, give 3.4 times it and are not checked."""
     wl = thermal_wave(4096, seed=0)
-    out = {}
+    out, rate = {}, {}
+    y = torch.tensor((np.arange(4096) + 0.5) / 4096, device=DEV)
+    mode = torch.exp(-2j * math.pi * y)
+
+    def amplitude(T):  # |T_k| of the wave's mode sin(2 pi y), float64 projection of the x-average
+        return float(torch.abs(2 * ((T - T.mean()).mean(dim=1) * mode).mean()))
+
     for storage, kernel in (("f64", "auto"), ("f32", "auto"), ("f32_dev", "auto"), ("f32_dev", "cell")):
         print(f"[thermal 4096] {storage} {kernel}", flush=True)
         s, _ = solver(wl, split=2, storage=storage, Pr=0.5, tau_ref=5e-5, kernel=kernel)
+        a0 = amplitude(s.moments(fields=True, sums=False)["T"])
         s.step(2000)
         m = s.moments(fields=True, sums=False)
-        out[storage if kernel == "auto" else f"{storage}_{kernel}"] = {k: m[k] for k in ("rho", "T")}
+        key = storage if kernel == "auto" else f"{storage}_{kernel}"
+        out[key] = {k: m[k] for k in ("rho", "T")}
+        rate[key] = math.log(a0 / amplitude(m["T"])) / ((2 * math.pi) ** 2 * 2000 * s.dt)
+        t_run = 2000 * s.dt
         s.close()
         del s, m
         torch.cuda.empty_cache()
+    # conductivity: the run lasts 0.5 % of the acoustic time, so the wave decays at the isochoric
+    # diffusivity gamma nu / Pr, over the elapsed time less the heat flux's start-up (tau_alpha = 1e-4)
+    expected = 1.4 * (5e-5 / 0.5) * (1.0 - 1e-4 / t_run)
+    print("[thermal 4096] decay rate / k^2 over gamma (nu/Pr)(1 - tau_alpha/t): "
+          + ", ".join(f"{k} {v / expected:.5f}" for k, v in rate.items()), flush=True)
+    assert abs(rate["f64"] / expected - 1) < 1e-3
+    assert abs(rate["f32_dev"] / expected - 1) < 3e-2 and abs(rate["f32_dev_cell"] / expected - 1) < 3e-2
     errs = {(st, k): rel(out[st][k], out["f64"][k]) for st in ("f32", "f32_dev", "f32_dev_cell") for k in ("rho", "T")}
     print("[thermal 4096] relative L2 against f64 after 2000 steps: "
           + ", ".join(f"{st} {k} {v:.2e}" for (st, k), v in errs.items()), flush=True)
@@ -614,12 +688,14 @@ def test_thermal_wave_4096_precision_2000_steps():
     assert errs["f32", "rho"] < 5e-5 and errs["f32", "T"] < 5e-5
 
 
-def test_adjoint_rejects_deviation_storage():
+@pytest.mark.parametrize("storage", ("bf16_dev", "fp16_dev"))
+def test_adjoint_rejects_16bit_storage(storage):
     wl = smooth_random(16, 16, seed=40)
-    s, _ = solver(wl, split=2, storage="f32_dev", tau_ref=0.02)
+    s, _ = solver(wl, split=2, storage=storage, tau_ref=0.02)
     lam = s.new_cotangent()
-    with pytest.raises(DVBMError):
+    with pytest.raises(DVBMError) as e:
         s.adjoint_step(s.state_buffer, lam, torch.empty_like(lam), torch.zeros(2, dtype=torch.float64, device=DEV))
+    assert e.value.code == dvbm.DVBM_EINVAL
     s.close()
 
 
