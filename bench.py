@@ -102,8 +102,8 @@ def write_profiles(trace_dir: str, fetch_csv: str, write_csv: str, bench_json: s
     """Summaries of the three PROFILE_COMMANDS runs under profiles/ (host only, no GPU).
 
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are calibrated against the
-    plain device copies that bench.py runs (copy_bandwidth: 4 GiB read + 4 GiB
-    written per dispatch): scale = known bytes / counter bytes.
+    streaming probes that bench.py runs (stream_ceiling: every dispatch reads
+    or writes 4 GiB, or both): scale = known bytes / counter bytes.
     """
     import csv
     import statistics
@@ -121,9 +121,9 @@ def write_profiles(trace_dir: str, fetch_csv: str, write_csv: str, bench_json: s
                 v = float(r["Counter_Value"]) * 1024.0
                 if kname + "<" in r["Kernel_Name"]:
                     vals.append(v)
-                elif "copy" in r["Kernel_Name"].lower():
+                elif "k_stream<" in r["Kernel_Name"]:
                     copies.append(v)
-        big = [v for v in copies if v >= 0.5 * max(copies)]  # the 4 GiB copies of copy_bandwidth()
+        big = [v for v in copies if v >= 0.5 * max(copies)]  # the probes that move 4 GiB this way
         return statistics.median(vals), statistics.median(big), len(vals), len(big)
 
     fetch, fcopy, nf, ncf = per_kernel(fetch_csv, "FETCH_SIZE")
@@ -187,9 +187,9 @@ def write_profiles(trace_dir: str, fetch_csv: str, write_csv: str, bench_json: s
         fh.write(f"    {PROFILE_COMMANDS['fetch']}\n    {PROFILE_COMMANDS['write']}\n\n")
         fh.write("| counter | kernel, per dispatch (median) | copy calibration | scaled bytes | algorithmic |\n")
         fh.write("|---|---|---|---|---|\n")
-        fh.write(f"| FETCH_SIZE | {fetch / 1024:.0f} KiB ({nf} dispatches) | 4 GiB copy reads {fcopy / 1024:.0f} KiB "
+        fh.write(f"| FETCH_SIZE | {fetch / 1024:.0f} KiB ({nf} dispatches) | 4 GiB probe reads {fcopy / 1024:.0f} KiB "
                  f"-> x{sf:.3f} | {fetch * sf / 1e9:.3f} GB | {alg / 2e9:.3f} GB read |\n")
-        fh.write(f"| WRITE_SIZE | {write / 1024:.0f} KiB ({nw} dispatches) | 4 GiB copy writes {wcopy / 1024:.0f} KiB "
+        fh.write(f"| WRITE_SIZE | {write / 1024:.0f} KiB ({nw} dispatches) | 4 GiB probe writes {wcopy / 1024:.0f} KiB "
                  f"-> x{sw:.3f} | {write * sw / 1e9:.3f} GB | {alg / 2e9:.3f} GB written |\n")
         tot = fetch * sf + write * sw
         fh.write(f"\nMeasured traffic per launch {tot / 1e9:.3f} GB = {tot / alg:.3f} x the algorithmic "
@@ -198,10 +198,28 @@ def write_profiles(trace_dir: str, fetch_csv: str, write_csv: str, bench_json: s
           f"(fetch x{sf:.3f}, write x{sw:.3f})")
 
 
-def time_mode(wl, phys, storage, steps, warmup, device, total_steps=0):
+def wave_amplitude(T):
+    """|T_k| of the y-mode sin(2 pi y / L) of a field T[y, x] (float64 projection of the x-average)."""
+    import math
+
+    import torch
+
+    ny = T.shape[0]
+    y = (torch.arange(ny, dtype=torch.float64, device=T.device) + 0.5) / ny
+    prof = (T - T.mean()).mean(dim=1)
+    re = (prof * torch.cos(2 * math.pi * y)).mean()
+    im = (prof * torch.sin(2 * math.pi * y)).mean()
+    return 2.0 * math.hypot(float(re), float(im))
+
+
+def time_mode(wl, phys, storage, steps, warmup, device, total_steps=0, amplitude=False):
     """Times ``steps`` launches after ``warmup``; then, untimed, runs on to
     ``total_steps`` in all before the fields are read (the precision sweep's
-    step count)."""
+    step count).  With ``amplitude``, the thermal wave's mode is also projected
+    at step 0 and at the end, and its decay rate over the run gives the thermal
+    diffusivity alpha (T_k(t) = T_k(0) exp(-alpha k^2 t))."""
+    import math
+
     import torch
 
     from paper_2510_04197_amd import Solver, make_params
@@ -209,6 +227,7 @@ def time_mode(wl, phys, storage, steps, warmup, device, total_steps=0):
     p = make_params(wl.nx, wl.ny, dx=wl.dx, dy=wl.dy, storage=storage, **phys)
     s = Solver(p, wl.rho, wl.ux, wl.uy, wl.T, device=device)
     stream = s.stream
+    amp0 = wave_amplitude(s.moments(fields=True, sums=False)["T"]) if amplitude else None
     s.step(warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -240,6 +259,10 @@ def time_mode(wl, phys, storage, steps, warmup, device, total_steps=0):
         "dt": s.dt,
     }
     out["frac"] = out["GBps"] / HBM_PEAK_GBPS
+    if amplitude:
+        t = max(total_steps, warmup + steps) * s.dt
+        amp1 = wave_amplitude(fields["T"])
+        out["alpha"] = math.log(amp0 / amp1) / ((2 * math.pi / wl.Ly) ** 2 * t) if amp1 > 0 else None
     s.close()
     del s
     torch.cuda.empty_cache()
@@ -284,6 +307,53 @@ def vortex_precision(device, nsteps=5000):
             out.setdefault(st, {})[f"rel_L2_{k}"] = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
             a8, b8 = pool(a[None, None], 8), pool(b[None, None], 8)
             out[st][f"rel_L2_{k}_128"] = float(torch.linalg.vector_norm(a8 - b8) / torch.linalg.vector_norm(b8))
+    return out
+
+
+def shock_vortex_runs(device, nsteps=8000, timed=50):
+    """The 2048 x 1024 shock-vortex workload (Ma_s 1.2, Ma_v 0.25, x zero-gradient, y periodic) for
+    the six (Pr, gamma) pairs Pr in {0.1, 0.71, 2}, gamma in {1.4, 5/3}: each float32 storage against
+    the float64-storage run after nsteps steps (relative L2 of rho and T, full grid and 8 x 8 block
+    averages), and the step throughput of each storage (HIP events over the first `timed` steps)."""
+    import torch
+
+    from paper_2510_04197_amd import Solver, make_params
+    from synth import shock_vortex
+
+    pool = torch.nn.functional.avg_pool2d
+    out = {"workload": "shock_vortex_2048x1024", "steps": nsteps, "reference": "float64-storage GPU run",
+           "pairs": []}
+    for Pr in (0.1, 0.71, 2.0):
+        for gamma in (1.4, 5.0 / 3.0):
+            wl = shock_vortex(2048, 1024, mach_s=1.2, mach_v=0.25, r_frac=0.075, gamma=gamma)
+            res, fields = {"Pr": Pr, "gamma": round(gamma, 6)}, {}
+            for st in ("f64", "f32", "f32_dev"):
+                p = make_params(wl.nx, wl.ny, dx=wl.dx, dy=wl.dy, split=2, storage=st, Pr=Pr, gamma=gamma,
+                                tau_ref=wl.phys["mu"], bc_x="zero_gradient", bc_y="periodic")
+                s = Solver(p, wl.rho, wl.ux, wl.uy, wl.T, device=device)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(s.stream)
+                s.step(timed)
+                e1.record(s.stream)
+                s.step(nsteps - timed)
+                m = s.moments(fields=True, sums=False)
+                ms = e0.elapsed_time(e1) / timed
+                res[f"{st}_MLUPS"] = round(wl.nx * wl.ny / (ms * 1e-3) / 1e6, 1)
+                res[f"{st}_frac"] = round(2 * 50 * STORAGE_BYTES[st] * wl.nx * wl.ny / (ms * 1e-3) / 1e9
+                                          / HBM_PEAK_GBPS, 4)
+                fields[st] = {k: m[k] for k in ("rho", "T")}
+                s.close()
+            for st in ("f32", "f32_dev"):
+                for k in ("rho", "T"):
+                    a, b = fields[st][k], fields["f64"][k]
+                    res[f"{st}_rel_L2_{k}"] = float("%.3g" % float(torch.linalg.vector_norm(a - b)
+                                                                   / torch.linalg.vector_norm(b)))
+                    a8, b8 = pool(a[None, None], 8), pool(b[None, None], 8)
+                    res[f"{st}_rel_L2_{k}_8x8"] = float("%.3g" % float(torch.linalg.vector_norm(a8 - b8)
+                                                                       / torch.linalg.vector_norm(b8)))
+            out["pairs"].append(res)
+            del fields
+            torch.cuda.empty_cache()
     return out
 
 
@@ -353,44 +423,79 @@ def adjoint_cost(device, n=256, nsteps=200, storage="f32", Ks=(10, 50)):
     return res
 
 
-def copy_bandwidth(device, nbytes=4 << 30, reps=5):
+def stream_ceiling(device, nbytes=4 << 30, reps=5):
+    """HBM GB/s of the library's plain streaming kernels (dvbm_stream_probe) over 4 GiB buffers:
+    copy and read with 16-byte lane accesses, plain and non-temporal, write with 16-byte accesses,
+    and copy with 4-byte ones (the width of the step kernels' loads).  The best copy is the
+    practical ceiling of a kernel that reads and writes about equally."""
     import torch
 
-    a = torch.empty(nbytes, dtype=torch.uint8, device=device)
-    b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    from paper_2510_04197_amd import dvbm
+
+    a = torch.zeros(nbytes, dtype=torch.uint8, device=device)
+    b = torch.zeros_like(a)
+    stream = torch.cuda.current_stream(device)
+    out = {}
+    for name, mode, width, moved in (("copy16", 0, 16, 2), ("copy16_nt", 4, 16, 2), ("read16", 1, 16, 1),
+                                     ("read16_nt", 5, 16, 1), ("write16", 2, 16, 1), ("copy4", 0, 4, 2)):
+        dvbm.stream_probe(a, b, nbytes, mode, width, stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            dvbm.stream_probe(a, b, nbytes, mode, width, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = round(moved * nbytes / (ms * 1e-3) / 1e9, 1)
     del a, b
     torch.cuda.empty_cache()
-    return 2 * nbytes / (ms * 1e-3) / 1e9
+    return out
 
 
-def cpu_baseline(n=256, steps=200):
-    """The FP64 oracle on the host: same workload family on an n x n sample."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n=256, steps=200, n1=128, steps1=20):
+    """The FP64 oracle on the host, timed on the thermal-wave family: an n x n
+    sample of `steps` steps with torch's default thread count, and an n1 x n1
+    sample of `steps1` steps on one thread (about the same CPU time)."""
     import numpy as np
     import torch
 
     from oracle import dvbm_oracle as O
     from synth import thermal_wave
 
-    wl = thermal_wave(n, seed=0)
-    cfg = O.Config(nx=n, ny=n, split=2, dx=wl.dx, dy=wl.dy, Pr=0.5, gamma=1.4, tau_ref=5e-5)
-    f, g = O.initial_state(wl.rho, wl.ux, wl.uy, wl.T, cfg)
-    dt = O.time_step(wl.rho, np.stack([wl.ux, wl.uy], -1), wl.T, cfg)
-    t0 = time.perf_counter()
-    O.run(f, g, cfg, dt, steps)
-    t = time.perf_counter() - t0
-    return {"value": n * n * steps / t / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(), "kind": "oracle",
+    def timed(m, k):
+        wl = thermal_wave(m, seed=0)
+        cfg = O.Config(nx=m, ny=m, split=2, dx=wl.dx, dy=wl.dy, Pr=0.5, gamma=1.4, tau_ref=5e-5)
+        f, g = O.initial_state(wl.rho, wl.ux, wl.uy, wl.T, cfg)
+        dt = O.time_step(wl.rho, np.stack([wl.ux, wl.uy], -1), wl.T, cfg)
+        t0 = time.perf_counter()
+        O.run(f, g, cfg, dt, k)
+        return time.perf_counter() - t0
+
+    threads = torch.get_num_threads()
+    t = timed(n, steps)
+    torch.set_num_threads(1)
+    try:
+        t1 = timed(n1, steps1)
+    finally:
+        torch.set_num_threads(threads)
+    return {"value": n * n * steps / t / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"thermal wave on a {n}x{n} periodic grid, {steps} float64 steps (split II, D2Q25)",
-            "seconds": t}
+            "seconds": t, "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "single_thread": {"value": n1 * n1 * steps1 / t1 / 1e6, "unit": "MLUPS", "seconds": t1,
+                              "sample": f"{n1}x{n1} grid, {steps1} steps, 1 thread"}}
 
 
 def main():
@@ -408,6 +513,7 @@ def main():
                     help="steps (timed ones included) after which the storage modes are compared with float64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
+    ap.add_argument("--no-shock-vortex", action="store_true", help="skip the 2048x1024 shock-vortex runs")
     ap.add_argument("--write-profiles", nargs=4, metavar=("TRACE_DIR", "FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
                     help="host only: summarise the rocprofv3 runs of PROFILE_COMMANDS into profiles/")
     args = ap.parse_args()
@@ -431,12 +537,13 @@ def main():
     wl, phys = workload_fields(args.workload)
     mode_list = [st for st in args.modes.split(",") if st and st != args.storage] if args.modes != "none" else []
     total = args.precision_steps if "f64" in mode_list + [args.storage] and mode_list else 0
-    main, main_fields = time_mode(wl, phys, args.storage, args.steps, args.warmup, device, total)
+    wave = args.workload == "thermal_wave_4096" and total > 0
+    main, main_fields = time_mode(wl, phys, args.storage, args.steps, args.warmup, device, total, amplitude=wave)
     print(f"[bench] {args.storage}: {main['MLUPS']:.1f} MLUPS, {main['GBps']:.1f} GB/s", file=sys.stderr, flush=True)
     modes = {}
     fields = {args.storage: main_fields}
     for st in mode_list:
-        modes[st], fields[st] = time_mode(wl, phys, st, args.steps, args.warmup, device, total)
+        modes[st], fields[st] = time_mode(wl, phys, st, args.steps, args.warmup, device, total, amplitude=wave)
         print(f"[bench] {st}: {modes[st]['MLUPS']:.1f} MLUPS, {modes[st]['GBps']:.1f} GB/s",
               file=sys.stderr, flush=True)
     precision = None
@@ -446,23 +553,47 @@ def main():
         for st, fl in fields.items():
             if st != "f64":
                 precision[st] = precision_errors(fl, fields["f64"])
+        if wave:
+            # decay rate of the thermal wave's mode in each storage's run.  The run lasts 4e-3 time
+            # units, 0.5 % of the acoustic time L / c, so the density has not moved: T decays at the
+            # isochoric diffusivity kappa / (rho c_v) = gamma nu / Pr (nu = mu / rho, rho ~ 1), and the
+            # heat flux, zero in the initial equilibrium, reaches its Fourier value after about the
+            # thermal relaxation time tau_alpha = mu / (p Pr), which the elapsed time loses
+            alphas = {args.storage: main["alpha"], **{k: v["alpha"] for k, v in modes.items()}}
+            nu_pr = phys["tau_ref"] / phys["Pr"]  # mu / (rho Pr), rho ~ 1 (mu = tau_ref p_ref, p_ref = 1)
+            tau_alpha = phys["tau_ref"] / phys["Pr"]  # mu / (p Pr), the wave being isobaric at p = 1
+            t_run = precision["steps"] * main["dt"]
+            expected = phys["gamma"] * nu_pr * (1.0 - tau_alpha / t_run)
+            precision["conductivity"] = {
+                "nu_over_Pr": nu_pr, "t": t_run,
+                "expected_decay_rate_over_k2": expected,
+                "note": "expected = gamma (nu/Pr) (1 - tau_alpha/t): isochoric decay over a run much shorter "
+                        "than the acoustic time, heat flux starting from zero",
+                **{st: {"alpha": a, "over_expected": a / expected if a else None,
+                        "rel_to_f64": (a / alphas["f64"] - 1) if a and alphas.get("f64") else None}
+                   for st, a in alphas.items()}}
     del fields, main_fields
     vortex = None
     if precision is not None:
         print("[bench] float32 precision on the 1024x1024 vortex, 5000 steps", file=sys.stderr, flush=True)
         vortex = vortex_precision(device)
+    shock = None
+    if not args.no_shock_vortex and args.workload == "thermal_wave_4096":
+        print("[bench] shock-vortex 2048x1024, six (Pr, gamma), 8000 steps", file=sys.stderr, flush=True)
+        shock = shock_vortex_runs(device)
     adjoint = None
     if not args.no_adjoint:
         print("[bench] adjoint cost on the 256x256 gradient workload", file=sys.stderr, flush=True)
         adjoint = adjoint_cost(device)
-    copy_gbps = copy_bandwidth(device)
+    ceiling = stream_ceiling(device)
 
     kernel_key = f"collide_advect/{args.workload}/{args.storage}"
     traffic = traffic_entry(kernel_key)
     roofline = {"bound": "hbm", "achieved": round(main["GBps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(main["frac"], 4), "traffic": traffic,
                 "bytes_per_update": main["bytes_per_update"], "kernel": step_kernel_name(args.storage, wl),
-                "copy_kernel_GBps": round(copy_gbps, 1)}
+                "copy_kernel_GBps": max(ceiling["copy16"], ceiling["copy16_nt"]), "stream_probe_GBps": ceiling,
+                "frac_of_copy": round(main["GBps"] / max(ceiling["copy16"], ceiling["copy16_nt"]), 4)}
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
@@ -490,6 +621,7 @@ def main():
                   for k, v in modes.items()},
         "precision": precision,
         "precision_vortex": vortex,
+        "shock_vortex": shock,
         "adjoint": adjoint,
     }
     print(json.dumps(line), flush=True)
