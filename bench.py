@@ -357,10 +357,13 @@ def shock_vortex_runs(device, nsteps=8000, timed=50):
     return out
 
 
-def adjoint_cost(device, n=256, nsteps=200, storage="f32", Ks=(10, 50)):
+def adjoint_cost(device, n=256, nsteps=200, storages=("f64", "f32", "f32_dev"), Ks=(10, 50)):
     """Gradient of L = sum (T(200 steps) - T_target)^2 w.r.t. T0, tau_ref, Pr on the 256^2 periodic
     Gaussian-bump workload: time of forward + checkpointed recomputation + reverse sweep, divided by
-    the time of the plain forward run (and with the recomputation on a second stream)."""
+    the time of the plain forward run, for each storage, checkpoint interval and cotangent type.
+    Each float32 storage's gradient is compared with the float64-storage one, which the tests check
+    against the oracle's reverse mode (1e-10); the "at 1e-5" ratio is that of the cheapest storage
+    whose gradient is within 1e-5 of it."""
     import numpy as np
     import torch
 
@@ -370,28 +373,7 @@ def adjoint_cost(device, n=256, nsteps=200, storage="f32", Ks=(10, 50)):
     bump = gaussian_bump(n, seed=7, amp=0.1, width=0.1)
     T0 = smooth_random(n, n, seed=13, amp_rho=0.0, amp_u=0.0, amp_T=0.05, mean_u=(0.0, 0.0)).T
     ones, zeros = np.ones((n, n)), np.zeros((n, n))
-    kw = dict(dx=1.0 / n, dy=1.0 / n, split=2, storage=storage, dt=1e-4)
     tau0, Pr = 2e-3, 0.71
-    tgt = rollout_temperature(torch.tensor(bump.T, device=device), torch.tensor(tau0, dtype=torch.float64),
-                              torch.tensor(Pr, dtype=torch.float64), ones, zeros, zeros, nsteps, K=50,
-                              **kw).detach()
-    p = make_params(n, n, tau_ref=tau0, Pr=Pr, **kw)
-
-    def forward_only():
-        s = Solver(p, ones, zeros, zeros, T0, device=device)
-        s.step(nsteps)
-        T = s.moments(fields=True, sums=False)["T"]
-        s.close()
-        return T
-
-    def with_gradient(K, overlap=False, cotangent="f64"):
-        T0t = torch.tensor(T0, device=device, requires_grad=True)
-        tau = torch.tensor(tau0, dtype=torch.float64, requires_grad=True)
-        prt = torch.tensor(Pr, dtype=torch.float64, requires_grad=True)
-        out = rollout_temperature(T0t, tau, prt, ones, zeros, zeros, nsteps, K=K, overlap=overlap,
-                                  cotangent=cotangent, **kw)
-        ((out - tgt) ** 2).sum().backward()
-        return T0t.grad, tau.grad, prt.grad
 
     def timed(fn, reps=3):
         fn()
@@ -402,24 +384,54 @@ def adjoint_cost(device, n=256, nsteps=200, storage="f32", Ks=(10, 50)):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / reps
 
-    t_fwd = timed(forward_only)
-    res = {"workload": f"gaussian bump {n}x{n} periodic, {nsteps} steps, {storage} storage",
-           "forward_s": t_fwd}
-    for K in Ks:
-        t = timed(lambda: with_gradient(K))
-        res[f"K{K}_s"] = t
-        res[f"K{K}_ratio"] = t / t_fwd
-        # float32 cotangents: time, and the gradient (T0, tau_ref, Pr) against the float64 one
-        t = timed(lambda: with_gradient(K, cotangent="f32"))
-        res[f"K{K}_f32_cotangent_ratio"] = t / t_fwd
-    g64, g32 = with_gradient(Ks[0]), with_gradient(Ks[0], cotangent="f32")
-    res["f32_cotangent_rel_err"] = {
-        "T0": float(torch.linalg.vector_norm(g32[0] - g64[0]) / torch.linalg.vector_norm(g64[0])),
-        "tau_ref": float(abs(g32[1] - g64[1]) / abs(g64[1])),
-        "Pr": float(abs(g32[2] - g64[2]) / abs(g64[2]))}
-    # the recomputation on a second stream
-    t = timed(lambda: with_gradient(Ks[0], overlap=True))
-    res[f"K{Ks[0]}_overlap_ratio"] = t / t_fwd
+    res = {"workload": f"gaussian bump {n}x{n} periodic, {nsteps} steps, dt 1e-4", "storages": {}}
+    grads = {}
+    # one target for every storage: the float64 run from the hidden bump
+    tgt = rollout_temperature(torch.tensor(bump.T, device=device), torch.tensor(tau0, dtype=torch.float64),
+                              torch.tensor(Pr, dtype=torch.float64), ones, zeros, zeros, nsteps, K=50,
+                              dx=1.0 / n, dy=1.0 / n, split=2, storage="f64", dt=1e-4).detach()
+    for storage in storages:
+        kw = dict(dx=1.0 / n, dy=1.0 / n, split=2, storage=storage, dt=1e-4)
+        p = make_params(n, n, tau_ref=tau0, Pr=Pr, **kw)
+
+        def forward_only():
+            s = Solver(p, ones, zeros, zeros, T0, device=device)
+            s.step(nsteps)
+            T = s.moments(fields=True, sums=False)["T"]
+            s.close()
+            return T
+
+        def with_gradient(K, cotangent="f64"):
+            T0t = torch.tensor(T0, device=device, requires_grad=True)
+            tau = torch.tensor(tau0, dtype=torch.float64, requires_grad=True)
+            prt = torch.tensor(Pr, dtype=torch.float64, requires_grad=True)
+            out = rollout_temperature(T0t, tau, prt, ones, zeros, zeros, nsteps, K=K, cotangent=cotangent, **kw)
+            ((out - tgt) ** 2).sum().backward()
+            return T0t.grad, tau.grad, prt.grad
+
+        t_fwd = timed(forward_only)
+        r = {"forward_s": t_fwd}
+        for K in Ks:
+            r[f"K{K}_ratio"] = timed(lambda: with_gradient(K)) / t_fwd
+            r[f"K{K}_f32_cotangent_ratio"] = timed(lambda: with_gradient(K, "f32")) / t_fwd
+        grads[storage] = with_gradient(Ks[0])
+        g32 = with_gradient(Ks[0], "f32")
+        r["f32_cotangent_rel_err"] = float(torch.linalg.vector_norm(g32[0] - grads[storage][0])
+                                           / torch.linalg.vector_norm(grads[storage][0]))
+        res["storages"][storage] = r
+    g64 = grads["f64"]
+    for storage in storages:
+        g = grads[storage]
+        res["storages"][storage]["gradient_rel_err_vs_f64"] = {
+            "T0": float(torch.linalg.vector_norm(g[0] - g64[0]) / torch.linalg.vector_norm(g64[0])),
+            "tau_ref": float(abs(g[1] - g64[1]) / abs(g64[1])), "Pr": float(abs(g[2] - g64[2]) / abs(g64[2]))}
+    for storage in storages:
+        r = res["storages"][storage]
+        r[f"K{Ks[0]}_gradient_s"] = r[f"K{Ks[0]}_ratio"] * r["forward_s"]
+    ok = [st for st in storages if max(res["storages"][st]["gradient_rel_err_vs_f64"].values()) <= 1e-5]
+    best = min(ok, key=lambda st: res["storages"][st][f"K{Ks[0]}_ratio"])
+    res["at_1e-5"] = {"storage": best, **{f"K{K}_ratio": res["storages"][best][f"K{K}_ratio"] for K in Ks},
+                      "storages_within_1e-5": ok}
     return res
 
 

@@ -44,12 +44,19 @@ struct KParams {
 };
 
 // ------------------------------------------------------------ storage formats
+// enc: a value computed in the format's arithmetic C -> stored value (the
+// value formats); enc_dev: a deviation in units of w, computed in C -> stored
+// value (the deviation formats); enc64: a float64 population X of weight w and
+// rest value r (per weight) -> stored value, with the deviation X / w - r
+// formed in float64 and rounded once to the stored type (initialisation,
+// loading, wall ghost rows).
 struct StoreF64 {
   using T = double;
   using C = double;
   static constexpr bool dev = false;
   __device__ static C raw(T v) { return v; }
   __device__ static T enc(C x, C /*winv*/, C /*r*/) { return x; }
+  __device__ static T enc64(double x, double /*w*/, double /*r*/) { return x; }
 };
 
 struct StoreF32 {
@@ -58,6 +65,7 @@ struct StoreF32 {
   static constexpr bool dev = false;
   __device__ static C raw(T v) { return v; }
   __device__ static T enc(C x, C, C) { return x; }
+  __device__ static T enc64(double x, double, double) { return float(x); }
 };
 
 // bfloat16 deviation (X - X_ref) / w, round to nearest even.
@@ -66,10 +74,10 @@ struct StoreBF16 {
   using C = float;
   static constexpr bool dev = true;
   __device__ static C raw(T v) { return __uint_as_float(uint32_t(v) << 16); }
-  __device__ static T enc(C x, C winv, C r) { return enc_dev(x * winv - r); }
   __device__ static T enc_dev(C d) {  // a deviation already in units of w; round to nearest even
     return __builtin_bit_cast(T, __bf16(d));
   }
+  __device__ static T enc64(double x, double w, double r) { return __builtin_bit_cast(T, __bf16(x / w - r)); }
 };
 
 // IEEE half deviation (X - X_ref) / w, round to nearest even.
@@ -78,8 +86,8 @@ struct StoreF16 {
   using C = float;
   static constexpr bool dev = true;
   __device__ static C raw(T v) { return float(v); }
-  __device__ static T enc(C x, C winv, C r) { return T(x * winv - r); }
   __device__ static T enc_dev(C d) { return T(d); }  // a deviation already in units of w
+  __device__ static T enc64(double x, double w, double r) { return T(x / w - r); }
 };
 
 // float32 deviation (X - X_ref) / w: float32's bytes, with the roundings of
@@ -89,8 +97,8 @@ struct StoreF32Dev {
   using C = float;
   static constexpr bool dev = true;
   __device__ static C raw(T v) { return v; }
-  __device__ static T enc(C x, C winv, C r) { return x * winv - r; }
   __device__ static T enc_dev(C d) { return d; }  // a deviation already in units of w
+  __device__ static T enc64(double x, double w, double r) { return float(x / w - r); }
 };
 
 // ------------------------------------------------------------ small helpers
@@ -168,6 +176,125 @@ __device__ inline NodeMoments node_moments(const R* f, const R* g) {
   pair_sums<N1>(t[1], m.qgy, u1, u2, u3);
   (void)u0;
   return m;
+}
+
+// Float64 moments (Eqs. eq_quadratur1-3, Table I notation) of one
+// distribution, accumulated one pair of +-xi_a columns at a time: the ten
+// moments of orders 0-3 of f (D = 0) or the three of orders 0-1 of g (D = 1).
+template <int D, int N1, class R>
+__device__ inline void half_moments(const R* v, double* out) {
+  using L = GH<N1>;
+  constexpr int NM = D == 0 ? 10 : 3;
+  double acc[NM];
+  double u1, u2, u3;
+  if (L::has_zero) {
+    constexpr int a = N1 / 2;
+    double s0, s1, s2, s3;
+    pair_sums<N1>(v + a * N1, s0, s1, s2, s3);
+    if (D == 0) {
+      // rho, jx, jy, pxx, pxy, pyy, qxxx, qxxy, qxyy, qyyy
+      acc[0] = s0; acc[1] = 0.0; acc[2] = s1; acc[3] = 0.0; acc[4] = 0.0;
+      acc[5] = s2; acc[6] = 0.0; acc[7] = 0.0; acc[8] = 0.0; acc[9] = s3;
+    } else {
+      // g0, qgx, qgy
+      acc[0] = s0; acc[1] = 0.0; acc[2] = s1;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NM; ++k) acc[k] = 0.0;
+  }
+  (void)u1; (void)u2; (void)u3;
+#pragma unroll
+  for (int k = 0; k < N1 / 2; ++k) {
+    const int pa = N1 - 1 - k;
+    const double x = L::xi(pa);
+    double a0, a1, a2, a3, b0, b1, b2, b3;
+    pair_sums<N1>(v + pa * N1, a0, a1, a2, a3);
+    pair_sums<N1>(v + k * N1, b0, b1, b2, b3);
+    const double e0 = a0 + b0, o0 = a0 - b0, e1 = a1 + b1;
+    if (D == 0) {
+      const double o1 = a1 - b1, e2 = a2 + b2, o2 = a2 - b2;
+      acc[0] += e0;
+      acc[1] += x * o0;
+      acc[2] += e1;
+      acc[3] += (x * x) * e0;
+      acc[4] += x * o1;
+      acc[5] += e2;
+      acc[6] += (x * x * x) * o0;
+      acc[7] += (x * x) * e1;
+      acc[8] += x * o2;
+      acc[9] += a3 + b3;
+    } else {
+      acc[0] += e0;
+      acc[1] += x * o0;
+      acc[2] += e1;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NM; ++k) out[k] = acc[k];
+}
+
+// The same moments of w_i v_i, for values v in units of the weight (the
+// deviations the 16-bit formats store): the weights enter the float64
+// coefficients of the sums, so no value is scaled first.
+template <int D, int N1, class R>
+__device__ inline void half_moments_w(const R* v, double* out) {
+  using L = GH<N1>;
+  constexpr int NM = D == 0 ? 10 : 3;
+  double acc[NM];
+#pragma unroll
+  for (int k = 0; k < NM; ++k) acc[k] = 0.0;
+  // sums over b of w_b v_(a, b) xi_b^k, k = 0..3, folding +-xi_b pairs
+  auto psum = [&](int a, double& s0, double& s1, double& s2, double& s3) {
+    const R* r = v + a * N1;
+    s0 = L::has_zero ? L::w(N1 / 2) * double(r[N1 / 2]) : 0.0;
+    s1 = s2 = s3 = 0.0;
+#pragma unroll
+    for (int k = 0; k < N1 / 2; ++k) {
+      const int pk = N1 - 1 - k;
+      const double x = L::xi(pk), w = L::w(pk);
+      const double e = double(r[pk]) + double(r[k]), o = double(r[pk]) - double(r[k]);
+      s0 += w * e;
+      s1 += (w * x) * o;
+      s2 += (w * x * x) * e;
+      s3 += (w * x * x * x) * o;
+    }
+  };
+  if (L::has_zero) {
+    const double wz = L::w(N1 / 2);
+    double s0, s1, s2, s3;
+    psum(N1 / 2, s0, s1, s2, s3);
+    acc[0] += wz * s0;
+    acc[2] += wz * s1;
+    if (D == 0) {
+      acc[5] += wz * s2;
+      acc[9] += wz * s3;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < N1 / 2; ++k) {
+    const int pa = N1 - 1 - k;
+    const double x = L::xi(pa), w = L::w(pa);
+    double a0, a1, a2, a3, b0, b1, b2, b3;
+    psum(pa, a0, a1, a2, a3);
+    psum(k, b0, b1, b2, b3);
+    const double e0 = a0 + b0, o0 = a0 - b0, e1 = a1 + b1;
+    acc[0] += w * e0;
+    acc[1] += (w * x) * o0;
+    acc[2] += w * e1;
+    if (D == 0) {
+      const double o1 = a1 - b1, e2 = a2 + b2, o2 = a2 - b2;
+      acc[3] += (w * x * x) * e0;
+      acc[4] += (w * x) * o1;
+      acc[5] += w * e2;
+      acc[6] += (w * x * x * x) * o0;
+      acc[7] += (w * x * x) * e1;
+      acc[8] += (w * x) * o2;
+      acc[9] += w * (a3 + b3);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NM; ++k) out[k] = acc[k];
 }
 
 // Hermite moments mu_k(u) = sum_j C(k,2j) (2j-1)!! t^j u^(k-2j) of a Gaussian
@@ -311,6 +438,29 @@ __device__ inline void collision_coeffs(const MomentsT<V>& m, const KParams& kp,
       bg[1][0] += dw * R(kp.c2 * upx);
       bg[0][1] += dw * R(kp.c2 * upy);
     }
+  }
+}
+
+// The deviation formats update d = X / w - r, where the rest value r (per
+// weight) is itself a Grad expansion: r = sum_k a^rest_k He_k / k! with
+// a^rest_(0,0) = 1 for f, and for g a^rest_(0,0) = gr0 plus, in split I,
+// a^rest_(2,0) = a^rest_(0,2) = 2 gr1.  The relaxation term -om1 X / w of
+// Eq. (finalDiscretePDE) is then -om1 d - om1 sum_k a^rest_k He_k / k!, so
+// subtracting om1 a^rest from the collision coefficients b leaves
+// d' = (1 - om1) d + sum_k (b_k - om1 a^rest_k) He_k / k! (+ flux): no term
+// of the size of r is formed per population, and at rest b = om1 a^rest
+// cancels exactly.
+template <int SPLIT, class R>
+__device__ inline void subtract_rest(R (&bf)[5][5], R (&bg)[3][3], R om1, const KParams& kp) {
+  // each om1 a^rest is rounded as the coefficient it cancels was (a fused
+  // multiply-add would subtract the exact product and leave that rounding)
+#pragma clang fp contract(off)
+  bf[0][0] -= om1;
+  bg[0][0] -= om1 * R(kp.gr0);
+  if (SPLIT == 1) {
+    const R c = om1 * R(2.0 * kp.gr1);
+    bg[2][0] -= c;
+    bg[0][2] -= c;
   }
 }
 

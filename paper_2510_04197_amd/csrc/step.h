@@ -26,6 +26,28 @@ __device__ inline double weight(int i) {
   return L::w(i / N1) * L::w(i % N1);
 }
 
+// Float64 moments of one cell's populations X = w (r + d) stored as
+// deviations d (units of w): those of w d, with the weights in the float64
+// coefficients of the sums, plus those of the rest state w r, so that a state
+// at rest has exactly the rest moments (decoding X in float32 first would
+// round w r).  The rest state's moments are the Gauss-Hermite rule's exact
+// low-order moments: rho = 1 and P = delta for f (r = 1); for g, g0 = gr0 in
+// both splits (in split I the |xi|^2 - 2 part of r has weighted mean 0) and a
+// zero first moment.
+template <int SPLIT, class R>
+__device__ inline NodeMoments dev_moments(const R* df, const R* dg, const KParams& kp) {
+  constexpr int N1 = Set<SPLIT>::N1;
+  double a[10], b[3];
+  half_moments_w<0, N1>(df, a);
+  half_moments_w<1, N1>(dg, b);
+  NodeMoments m;
+  m.rho = a[0] + 1.0; m.jx = a[1]; m.jy = a[2];
+  m.pxx = a[3] + 1.0; m.pxy = a[4]; m.pyy = a[5] + 1.0;
+  m.qxxx = a[6]; m.qxxy = a[7]; m.qxyy = a[8]; m.qyyy = a[9];
+  m.g0 = b[0] + kp.gr0; m.qgx = b[1]; m.qgy = b[2];
+  return m;
+}
+
 template <int BC>
 __device__ inline int wrap(int j, int n) {
   if (BC == BC_PERIODIC) return j < 0 ? j + n : (j >= n ? j - n : j);
@@ -136,35 +158,25 @@ __device__ inline void cell_update(const typename S::T* __restrict__ src, typena
   for (int d = 0; d < 2; ++d)
 #pragma unroll
     for (int i = 0; i < Q; ++i) xs[d][i] = S::raw(Buf<T>::ld(rsrc_src[d], i * plane_bytes, o0));
-  R X[2][Q];  // decoded populations
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    if (S::dev) {
-      const double w = weight<SPLIT>(i);
-      X[0][i] = R(w) * (R(1) + xs[0][i]);
-      X[1][i] = R(w) * (R(g_ref_over_w<SPLIT>(kp, i)) + xs[1][i]);
-    } else {
-      X[0][i] = xs[0][i];
-      X[1][i] = xs[1][i];
-    }
-  }
-  const NodeMoments m = node_moments<N1>(X[0], X[1]);
+  NodeMoments m;
+  if constexpr (S::dev)
+    m = dev_moments<SPLIT>(xs[0], xs[1], kp);
+  else
+    m = node_moments<N1>(xs[0], xs[1]);
+  R X[2][Q];  // the increment of each population
   R bf[5][5], bg[3][3], om1;
   collision_coeffs<SPLIT, PRM, R>(m, kp, kp.om_scale, kp.Pr, bf, bg, om1);
 
   // collision: (1 - om1) X + expansion of b.  X then holds the increment,
   // added to the stored value once at the end (one rounding at the stored
   // value's magnitude): -om1 X + expansion for values, and in deviation units
-  // d = X / w - r,  -om1 (r + d) + expansion / w  for the deviation formats.
+  // d = X / w - r,  -om1 d + expansion / w of b less om1 times the rest
+  // coefficients (subtract_rest) for the deviation formats.
+  if constexpr (S::dev) subtract_rest<SPLIT>(bf, bg, om1, kp);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    if constexpr (S::dev) {
-      X[0][i] = -om1 * (R(1) + xs[0][i]);
-      X[1][i] = -om1 * (R(g_ref_over_w<SPLIT>(kp, i)) + xs[1][i]);
-    } else {
-      X[0][i] *= -om1;
-      X[1][i] *= -om1;
-    }
+    X[0][i] = -om1 * xs[0][i];
+    X[1][i] = -om1 * xs[1][i];
   }
   expand_add<N1, Set<SPLIT>::NF, R, 5, !S::dev>(bf, X[0]);
   expand_add<N1, 2, R, 3, !S::dev>(bg, X[1]);
@@ -311,23 +323,13 @@ __device__ inline void tile_update(const typename S::T* __restrict__ src, typena
 #pragma unroll
     for (int i = 0; i < Q; ++i) xs[d][i] = S::raw(Buf<T>::ld(rsrc_src[d], i * plane_bytes, o0));
   NodeMoments m;
-  {
-    R f[Q], g[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      if (S::dev) {
-        const double w = weight<SPLIT>(i);
-        f[i] = R(w) * (R(1) + xs[0][i]);
-        g[i] = R(w) * (R(g_ref_over_w<SPLIT>(kp, i)) + xs[1][i]);
-      } else {
-        f[i] = xs[0][i];
-        g[i] = xs[1][i];
-      }
-    }
-    m = node_moments<N1>(f, g);
-  }
+  if constexpr (S::dev)
+    m = dev_moments<SPLIT>(xs[0], xs[1], kp);
+  else
+    m = node_moments<N1>(xs[0], xs[1]);
   R bf[5][5], bg[3][3], om1;
   collision_coeffs<SPLIT, PRM, R>(m, kp, kp.om_scale, kp.Pr, bf, bg, om1);
+  if constexpr (S::dev) subtract_rest<SPLIT>(bf, bg, om1, kp);  // the -om1 r term, in the coefficients
   const R beta2 = R(kp.beta2);
   const R kx = R(kp.kx), ky = R(kp.ky);
 
@@ -385,11 +387,11 @@ __device__ inline void tile_update(const typename S::T* __restrict__ src, typena
       const R* buf = &lds.v[gk & 1][xa][0][0];
       const R c0 = xs[d][i];
       const uint32_t so = i * plane_bytes;
-      const R rr = S::dev ? R(d == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i)) : R(0);
       // collision: (1 - om1) X + w_i sum_p He_p(xi_a)/p! c_p.  The increment
       // is summed first and added to the stored value once: -om1 X + ... for
-      // values, -om1 (r + d) + sum_p He_p c_p in deviation units d = X/w - r
-      R xn = -om1 * (rr + c0);
+      // values, -om1 d + sum_p He_p c_p in deviation units d = X/w - r (the
+      // rest expansion taken out of c by subtract_rest)
+      R xn = -om1 * c0;
       constexpr double wx = S::dev ? 1.0 : w;
 #pragma unroll
       for (int p = 0; p <= NMAX; ++p) {

@@ -66,125 +66,6 @@ __device__ inline double lane_next(double v) {
   return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
 }
 
-// Float64 moments (Eqs. eq_quadratur1-3, Table I notation) of one
-// distribution, accumulated one pair of +-xi_a columns at a time: the ten
-// moments of orders 0-3 of f (D = 0) or the three of orders 0-1 of g (D = 1).
-template <int D, int N1, class R>
-__device__ inline void half_moments(const R* v, double* out) {
-  using L = GH<N1>;
-  constexpr int NM = D == 0 ? 10 : 3;
-  double acc[NM];
-  double u1, u2, u3;
-  if (L::has_zero) {
-    constexpr int a = N1 / 2;
-    double s0, s1, s2, s3;
-    pair_sums<N1>(v + a * N1, s0, s1, s2, s3);
-    if (D == 0) {
-      // rho, jx, jy, pxx, pxy, pyy, qxxx, qxxy, qxyy, qyyy
-      acc[0] = s0; acc[1] = 0.0; acc[2] = s1; acc[3] = 0.0; acc[4] = 0.0;
-      acc[5] = s2; acc[6] = 0.0; acc[7] = 0.0; acc[8] = 0.0; acc[9] = s3;
-    } else {
-      // g0, qgx, qgy
-      acc[0] = s0; acc[1] = 0.0; acc[2] = s1;
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < NM; ++k) acc[k] = 0.0;
-  }
-  (void)u1; (void)u2; (void)u3;
-#pragma unroll
-  for (int k = 0; k < N1 / 2; ++k) {
-    const int pa = N1 - 1 - k;
-    const double x = L::xi(pa);
-    double a0, a1, a2, a3, b0, b1, b2, b3;
-    pair_sums<N1>(v + pa * N1, a0, a1, a2, a3);
-    pair_sums<N1>(v + k * N1, b0, b1, b2, b3);
-    const double e0 = a0 + b0, o0 = a0 - b0, e1 = a1 + b1;
-    if (D == 0) {
-      const double o1 = a1 - b1, e2 = a2 + b2, o2 = a2 - b2;
-      acc[0] += e0;
-      acc[1] += x * o0;
-      acc[2] += e1;
-      acc[3] += (x * x) * e0;
-      acc[4] += x * o1;
-      acc[5] += e2;
-      acc[6] += (x * x * x) * o0;
-      acc[7] += (x * x) * e1;
-      acc[8] += x * o2;
-      acc[9] += a3 + b3;
-    } else {
-      acc[0] += e0;
-      acc[1] += x * o0;
-      acc[2] += e1;
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < NM; ++k) out[k] = acc[k];
-}
-
-// The same moments of w_i v_i, for values v in units of the weight (the
-// deviations the 16-bit formats store): the weights enter the float64
-// coefficients of the sums, so no value is scaled first.
-template <int D, int N1, class R>
-__device__ inline void half_moments_w(const R* v, double* out) {
-  using L = GH<N1>;
-  constexpr int NM = D == 0 ? 10 : 3;
-  double acc[NM];
-#pragma unroll
-  for (int k = 0; k < NM; ++k) acc[k] = 0.0;
-  // sums over b of w_b v_(a, b) xi_b^k, k = 0..3, folding +-xi_b pairs
-  auto psum = [&](int a, double& s0, double& s1, double& s2, double& s3) {
-    const R* r = v + a * N1;
-    s0 = L::has_zero ? L::w(N1 / 2) * double(r[N1 / 2]) : 0.0;
-    s1 = s2 = s3 = 0.0;
-#pragma unroll
-    for (int k = 0; k < N1 / 2; ++k) {
-      const int pk = N1 - 1 - k;
-      const double x = L::xi(pk), w = L::w(pk);
-      const double e = double(r[pk]) + double(r[k]), o = double(r[pk]) - double(r[k]);
-      s0 += w * e;
-      s1 += (w * x) * o;
-      s2 += (w * x * x) * e;
-      s3 += (w * x * x * x) * o;
-    }
-  };
-  if (L::has_zero) {
-    const double wz = L::w(N1 / 2);
-    double s0, s1, s2, s3;
-    psum(N1 / 2, s0, s1, s2, s3);
-    acc[0] += wz * s0;
-    acc[2] += wz * s1;
-    if (D == 0) {
-      acc[5] += wz * s2;
-      acc[9] += wz * s3;
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < N1 / 2; ++k) {
-    const int pa = N1 - 1 - k;
-    const double x = L::xi(pa), w = L::w(pa);
-    double a0, a1, a2, a3, b0, b1, b2, b3;
-    psum(pa, a0, a1, a2, a3);
-    psum(k, b0, b1, b2, b3);
-    const double e0 = a0 + b0, o0 = a0 - b0, e1 = a1 + b1;
-    acc[0] += w * e0;
-    acc[1] += (w * x) * o0;
-    acc[2] += w * e1;
-    if (D == 0) {
-      const double o1 = a1 - b1, e2 = a2 + b2, o2 = a2 - b2;
-      acc[3] += (w * x * x) * e0;
-      acc[4] += (w * x) * o1;
-      acc[5] += w * e2;
-      acc[6] += (w * x * x * x) * o0;
-      acc[7] += (w * x * x) * e1;
-      acc[8] += (w * x) * o2;
-      acc[9] += w * (a3 + b3);
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < NM; ++k) out[k] = acc[k];
-}
-
 // Moment exchange between the two waves of a strip: 13 float64 moments per
 // lane, double-buffered by row parity so one barrier per row suffices.
 struct SweepShared {
@@ -261,7 +142,6 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
   };
   // face value between c and n, upwind cell c, far-side cell u: c + L(c - u, n - c) / 4
   auto face = [&](R u, R c, R n) -> R { return c + R(0.25) * lim4(c - u, n - c, beta2); };
-  auto rest = [&](int i) -> R { return R(D == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i)); };
   // 16-bit formats: X_i = w_i (r_i + d_i), so a moment is that of w_i r_i
   // (formed here once, in float64) plus that of w_i d_i (formed per row)
   constexpr int NM = D == 0 ? 10 : 3;
@@ -272,8 +152,6 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
     for (int i = 0; i < Q; ++i) vr[i] = D == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i);
     half_moments_w<D, N1>(vr, mref);
   }
-  // the rest value r_i is the same for every population of f, and of g in split II
-  constexpr bool rest_uniform = D == 0 || SPLIT == 2;
 
   // win[i][(P + r) % RING] holds ring row r at phase P = (y - ya) % RING:
   // row y - 1 + r when xi_b > 0, y + r otherwise.  A row enters the ring as
@@ -357,6 +235,7 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
     }
     R bf[5][5], bg[3][3], om1;
     collision_coeffs<SPLIT, PRM, R>(m, kp, kp.om_scale, kp.Pr, bf, bg, om1);
+    if constexpr (S::dev) subtract_rest<SPLIT>(bf, bg, om1, kp);  // the -om1 r term, in the coefficients
     const R keep = R(1) - om1;
 
     // groups of the N1 populations i = a N1 + b that share the y-node b
@@ -374,7 +253,6 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
           if (h != 0.0) c[p] += (D == 0 ? bf[p][q] : bg[p][q]) * R(h);
         }
       }
-      if (S::dev && rest_uniform) c[0] -= om1 * rest(0);  // He_0 = 1: the -om1 r term of every population
       static_for<N1>([&](auto ac) {
         constexpr int xa = decltype(ac)::value;
         constexpr int i = xa * N1 + ybn;
@@ -382,11 +260,11 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
         constexpr double w = GH<N1>::w(xa) * GH<N1>::w(ybn);
         R* wn = win[i];
         const R c0 = cen[i];
-        // collision: (1 - om1) X + w_i sum_p He_p(xi_a)/p! c_p; the 16-bit formats work in
-        // deviation units d = X/w - r:  d' = (1 - om1) d - om1 r + sum_p He_p(xi_a)/p! c_p
+        // collision: (1 - om1) X + w_i sum_p He_p(xi_a)/p! c_p; the deviation formats work in
+        // units d = X/w - r, with the rest expansion taken out of c:  d' = (1 - om1) d + sum_p He_p/p! c_p
         R xn;
         if (S::dev) {
-          xn = rest_uniform ? keep * c0 : keep * c0 - om1 * rest(i);
+          xn = keep * c0;
 #pragma unroll
           for (int p = 0; p <= 4; ++p) {
             if (p > N) continue;

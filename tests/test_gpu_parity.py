@@ -563,6 +563,37 @@ def test_stiff_relaxation_rejected():
     assert e.value.code == dvbm.DVBM_ESTIFF
 
 
+@pytest.mark.parametrize("kernel", ("cell", "sweep", "tile"))
+@pytest.mark.parametrize("storage", ("f32_dev", "bf16_dev", "fp16_dev"))
+@pytest.mark.parametrize("split", (1, 2))
+def test_rest_state_stores_zero_deviations(split, storage, kernel):
+    """The rest equilibrium (rho = 1, u = 0, T = T_ref) is the deviation
+    formats' reference, so its stored deviations (X / w - r, formed in float64
+    and rounded once) are zero up to the float64 residue of X / w - r, and stay
+    so over 10 steps.  Rounding X to float32 before subtracting would leave
+    about 6e-8."""
+    wl = uniform(70, 9)
+    s, p = solver(wl, split=split, storage=storage, tau_ref=0.02, cfl=0.1, T_ref=1.0, kernel=kernel)
+    dt = {"f32_dev": torch.float32, "bf16_dev": torch.bfloat16, "fp16_dev": torch.float16}[storage]
+    pitch = dvbm.load_library().dvbm_pitch(ctypes.byref(p))
+
+    def devs():
+        return s.state_buffer.view(dt).reshape(2 * s.Q, p.ny, pitch)[:, :, : p.nx].float()
+
+    d0 = devs()
+    assert float(d0[: s.Q].abs().max()) == 0.0  # f: X / w = 1 exactly
+    assert float(d0.abs().max()) <= 1e-12
+    hist = []
+    for _ in range(10):
+        s.step(1)
+        d = devs()
+        hist.append((float(d[: s.Q].abs().max()), float(d[s.Q:].abs().max()),
+                     int(d[s.Q:].abs().amax(dim=(1, 2)).argmax())))
+    print(f"[rest state] split {split} {storage} {kernel}: max |d| per step (f, g, worst g plane) {hist}", flush=True)
+    assert max(max(f, g) for f, g, _ in hist) <= 1e-12
+    s.close()
+
+
 @pytest.mark.parametrize("storage", ("f64", "f32", "bf16_dev", "f32_dev"))
 def test_step_from_matches_step(storage):
     """dvbm_step_from(src, dst) computes the same step as dvbm_step and leaves the handle's state alone."""
@@ -649,9 +680,11 @@ def test_thermal_wave_4096_precision_2000_steps():
     at the isochoric diffusivity kappa / (rho c_v) = gamma nu / Pr, less the
     start-up of the heat flux from the initial equilibrium (about tau_alpha =
     mu / (p Pr)): rate = gamma (nu / Pr)(1 - tau_alpha / t).  The float64 run
-    gives it within 1e-3 (measured 5e-4), float32 deviations within 3 %
-    (measured 1.5 %); float32 values, whose drift is of the size of the
-    2e-5 decay, give 3.4 times it and are not checked."""
+    gives it within 1e-3 (measured 5e-4).  The decay is 1.1e-6 in T over the
+    run, near what float32 storage resolves: float32 deviations give it within
+    5 % (measured +1.5 % and +3.2 % for two rounding orders of the same
+    arithmetic, -1.6 % on the per-cell kernel); float32 values, whose drift is
+    of the size of the decay, give 2.5 to 3.4 times it and are not checked."""
     wl = thermal_wave(4096, seed=0)
     out, rate = {}, {}
     y = torch.tensor((np.arange(4096) + 0.5) / 4096, device=DEV)
@@ -678,14 +711,14 @@ def test_thermal_wave_4096_precision_2000_steps():
     expected = 1.4 * (5e-5 / 0.5) * (1.0 - 1e-4 / t_run)
     print("[thermal 4096] decay rate / k^2 over gamma (nu/Pr)(1 - tau_alpha/t): "
           + ", ".join(f"{k} {v / expected:.5f}" for k, v in rate.items()), flush=True)
-    assert abs(rate["f64"] / expected - 1) < 1e-3
-    assert abs(rate["f32_dev"] / expected - 1) < 3e-2 and abs(rate["f32_dev_cell"] / expected - 1) < 3e-2
     errs = {(st, k): rel(out[st][k], out["f64"][k]) for st in ("f32", "f32_dev", "f32_dev_cell") for k in ("rho", "T")}
     print("[thermal 4096] relative L2 against f64 after 2000 steps: "
           + ", ".join(f"{st} {k} {v:.2e}" for (st, k), v in errs.items()), flush=True)
     assert errs["f32_dev", "rho"] < 1e-5 and errs["f32_dev", "T"] < 1e-5
     assert errs["f32_dev_cell", "rho"] < 1e-5 and errs["f32_dev_cell", "T"] < 1e-5
     assert errs["f32", "rho"] < 5e-5 and errs["f32", "T"] < 5e-5
+    assert abs(rate["f64"] / expected - 1) < 1e-3
+    assert abs(rate["f32_dev"] / expected - 1) < 5e-2 and abs(rate["f32_dev_cell"] / expected - 1) < 5e-2
 
 
 @pytest.mark.parametrize("storage", ("bf16_dev", "fp16_dev"))
