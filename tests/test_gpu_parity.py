@@ -1083,3 +1083,113 @@ def test_shear_viscosity_on_a_flow(split, Pr, mach):
     print(f"[shear] split {split} Pr {Pr} Ma {mach}: nu / (mu - U^2 dt/2) - 1 = {nu / expected - 1:.2e}"
           f" (forward-Euler term {0.5 * U * U * dt / mu:.1e} of nu)", flush=True)
     assert abs(nu - expected) < 0.01 * mu  # measured 5e-5 to 7.7e-4 of nu
+
+
+# ---------------------------------------------------------------- the paper's speed-of-sound test (Sec. IV)
+def front_crossing(q, xc, level, dx, window=25):
+    """Position (unwrapped around xc) where the periodic cell profile q falls
+    through `level`, by linear interpolation between cell centres; of the
+    downward crossings within `window` cells of xc, the nearest to xc."""
+    n = len(q)
+    k0 = int(np.floor(xc / dx - 0.5))
+    best = float("nan")
+    for k in range(k0 - window, k0 + window):
+        a, b = q[k % n], q[(k + 1) % n]
+        if a >= level > b:
+            xk = (k + 0.5 + (a - level) / (a - b)) * dx
+            if not abs(xk - xc) >= abs(best - xc):
+                best = xk
+    return best
+
+
+def pressure_front_speed(split, theta, mach, gamma, Pr, n=512, amp=1e-6, cfl=0.01, run=0.15):
+    """The paper's dispersion test: on a periodic pseudo-1-D line of n cells,
+    p = 1 + amp for x <= 1/2 and 1 beyond, uniform T = theta T_ref and
+    u = Ma sqrt(gamma R T).  The step at x = 1/2 splits into a right- and a
+    left-running acoustic front, both pressure drops of amp / 2, moving at
+    u + c and u - c (the entropy part carries no pressure), with a plateau of
+    amp / 2 between them.  Each front is located where p - 1 falls through
+    its mid level (3 amp / 4 for the left-runner, amp / 4 for the right-runner;
+    linear interpolation, the crossing nearest to where the front should be),
+    at 1/3 and at the end of the run (t = 0.15 / c, before any front meets
+    another), so c = (v_+ - v_-) / 2 and the flow speed (v_+ + v_-) / 2 follow
+    from the two front speeds.  mu = max(5e-5, 2 dt p) keeps dt / tau_1 <= 0.5
+    (CFL 0.01 gives dt / tau > 2 in cold flows at mu = 5e-5).  Returns
+    (c / sqrt(gamma R T) - 1, measured flow speed / u - 1 (at rest: the
+    measured flow speed / c), whether the run stayed finite)."""
+    ny = 4
+    dx = 1.0 / n
+    x = (np.arange(n) + 0.5) * dx
+    c0 = math.sqrt(gamma * theta)
+    U = mach * c0
+    p0 = np.where(x <= 0.5, 1.0 + amp, 1.0)
+    T = np.full((ny, n), theta)
+    rho = np.repeat((p0 / theta)[None, :], ny, 0)
+    dt_est = cfl * dx / (abs(U) + c0)
+    Pr_eff = Pr if Pr > 1 else 1.0
+    mu = max(5e-5, 2.0 * dt_est * (1.0 + amp) * Pr_eff)
+    s = Solver(make_params(n, ny, dx=dx, dy=dx, split=split, storage="f64", Pr=Pr, gamma=gamma, tau_ref=mu, cfl=cfl),
+               rho, np.full((ny, n), U), np.zeros((ny, n)), T, device=DEV)
+    dt = s.dt
+    t_end = run / c0
+    n_end = int(round(t_end / dt))
+    n_mid = n_end // 3
+    pos = {}
+
+    def locate(t):
+        try:
+            m = s.moments(fields=True, sums=True)  # raises ENAN on a non-finite state
+        except DVBMError:
+            return None
+        pr = ((m["rho"] * m["T"]).mean(dim=0).cpu().numpy() - 1.0) / amp  # (p - 1) / amp, R = 1
+        return [front_crossing(pr, 0.5 + v * t, level, dx) for v, level in ((U + c0, 0.25), (U - c0, 0.75))]
+
+    s.step(n_mid)
+    pos[1] = (n_mid * dt, locate(n_mid * dt))
+    ok = pos[1][1] is not None
+    if ok:
+        s.step(n_end - n_mid)
+        pos[2] = (n_end * dt, locate(n_end * dt))
+        ok = pos[2][1] is not None
+    s.close()
+    if not ok:
+        return float("nan"), float("nan"), False
+    (t1, (r1, l1)), (t2, (r2, l2)) = pos[1], pos[2]
+    vr, vl = (r2 - r1) / (t2 - t1), (l2 - l1) / (t2 - t1)
+    c = 0.5 * (vr - vl)
+    u = 0.5 * (vr + vl)
+    return c / c0 - 1.0, (u / U - 1.0) if U else u / c0, True
+
+
+@pytest.mark.parametrize("Pr", (0.5, 1.0, 2.0))
+@pytest.mark.parametrize("gamma", (5.0 / 3.0, 4.0 / 3.0), ids=("5/3", "4/3"))
+@pytest.mark.parametrize("split", (1, 2))
+def test_pressure_front_speed_paper_ranges(split, gamma, Pr):
+    """The paper's speed-of-sound test (Sec. IV, dispersion): a pressure step
+    of 1e-6 on 512 cells at CFL 0.01, both fronts tracked (pressure_front_speed).
+    Measured over both gamma and the three Pr:
+      - at T_ref, Mach 0 to 3: |c / sqrt(gamma R T) - 1| at most 0.29 % to
+        Mach 2.5 (split I) and 2 (split II), 0.29 % and 0.82 % at Mach 3
+        (finite to Mach 3.5: 0.56 % and 2.0 %); the flow speed within 0.23 %;
+      - at rest, split I (D2Q16) from T / T_ref = 0.03 to 300: 1.15 % at 0.03,
+        at most 0.30 % from 0.1 to 100, 0.75 % at 300 (5.3 % at 0.01);
+        split II (D2Q25) from 0.03 to 30: 1.45 % at 0.03, at most 0.41 % from
+        0.1 to 10, 0.87 % at 30 (8.8 % at 0.01), and the run diverges at
+        100 T_ref: four and three orders of temperature within about 1 %,
+        the ranges the paper reports for the two velocity sets."""
+    mach_pts = [(1.0, m, 4e-3) for m in (0.0, 1.0, 2.0)] + [(1.0, 3.0, 1.2e-2)]
+    if split == 1:
+        temp_pts = [(0.01, 0.0, 8e-2), (0.03, 0.0, 1.6e-2), (0.1, 0.0, 4e-3), (10.0, 0.0, 4e-3),
+                    (100.0, 0.0, 4e-3), (300.0, 0.0, 1e-2)]
+    else:
+        temp_pts = [(0.03, 0.0, 2e-2), (0.1, 0.0, 6e-3), (0.3, 0.0, 4e-3), (10.0, 0.0, 4e-3), (30.0, 0.0, 1.2e-2)]
+    for theta, mach, bound in mach_pts + temp_pts:
+        e, u, ok = pressure_front_speed(split, theta, mach, gamma, Pr)
+        print(f"[pressure front] split {split} gamma {gamma:.3f} Pr {Pr} T/T_ref {theta} Ma {mach}: "
+              f"c / sqrt(gamma R T) - 1 = {e:.2e}, flow speed error {u:.1e}", flush=True)
+        assert ok and abs(e) < bound, (theta, mach, e)
+        assert abs(u) < 5e-3, (theta, mach, u)
+    if split == 2:
+        assert not pressure_front_speed(split, 100.0, 0.0, gamma, Pr)[2]  # D2Q25's upper temperature limit
+
+

@@ -729,3 +729,48 @@ def test_max_relaxation_rate_by_hand(visc_mode, Pr):
     cfg = O.Config(nx=5, ny=3, R=2.0, tau_ref=1e-3, p_ref=2.0, Pr=Pr, visc_mode=visc_mode)
     want = (0.13 if visc_mode == O.CONST_MU else 1e-2) * (Pr if Pr > 1 else 1.0)
     assert abs(O.max_relaxation_rate(rho, T, cfg, 1e-5) - want) <= 1e-14 * want
+
+
+def test_pressure_front_speed_at_mach_2():
+    """The paper's speed-of-sound test (Sec. IV) on the oracle, reduced to 128
+    cells: a pressure step of 1e-6 at CFL 0.01 on a Mach-2 flow at T_ref
+    (split II, gamma 4/3, Pr 1).  The step at x = 1/2 splits into a left- and
+    a right-running drop of 5e-7 with a plateau between them; each front is
+    located where (p - 1) / 1e-6 falls through its mid level (0.75, 0.25), at
+    1/3 and at the end of 0.15 / c, and c = (v_+ - v_-) / 2, u = (v_+ + v_-) / 2
+    match sqrt(gamma R T) and the flow within 3 %."""
+    n, ny, amp, gamma, mach = 128, 4, 1e-6, 4.0 / 3.0, 2.0
+    dx = 1.0 / n
+    x = (np.arange(n) + 0.5) * dx
+    c0 = math.sqrt(gamma)
+    U = mach * c0
+    p0 = np.where(x <= 0.5, 1.0 + amp, 1.0)
+    rho = np.repeat(p0[None, :], ny, 0)
+    ux, uy, T = np.full((ny, n), U), np.zeros((ny, n)), np.ones((ny, n))
+    cfg = O.Config(nx=n, ny=ny, split=2, dx=dx, dy=dx, gamma=gamma, Pr=1.0, cfl=0.01)
+    dt = O.time_step(rho, np.stack([ux, uy], -1), T, cfg)
+    cfg.tau_ref = max(5e-5, 2.0 * dt)
+    f, g = O.initial_state(rho, ux, uy, T, cfg)
+    v, _ = O.velocity_set(cfg)
+    n_end = int(round(0.15 / c0 / dt))
+    n_mid = n_end // 3
+
+    def fronts(f, g, t):
+        r, _, _, Tt = O.macroscopic(f, g, v, cfg)
+        q = ((r * cfg.R * Tt).mean(0).numpy() - 1.0) / amp
+        out = []
+        for vel, level in ((U + c0, 0.25), (U - c0, 0.75)):
+            xc = 0.5 + vel * t
+            k0 = int(np.floor(xc / dx - 0.5))
+            xs = [(k + 0.5 + (q[k % n] - level) / (q[k % n] - q[(k + 1) % n])) * dx
+                  for k in range(k0 - 8, k0 + 8) if q[k % n] >= level > q[(k + 1) % n]]
+            out.append(min(xs, key=lambda z: abs(z - xc)))
+        return out
+
+    f, g = O.run(f, g, cfg, dt, n_mid)
+    r1, l1 = fronts(f, g, n_mid * dt)
+    f, g = O.run(f, g, cfg, dt, n_end - n_mid)
+    r2, l2 = fronts(f, g, n_end * dt)
+    vr, vl = (r2 - r1) / ((n_end - n_mid) * dt), (l2 - l1) / ((n_end - n_mid) * dt)
+    c, u = 0.5 * (vr - vl), 0.5 * (vr + vl)
+    assert abs(c / c0 - 1) < 3e-2 and abs(u / U - 1) < 3e-2, (c / c0, u / U)
