@@ -71,7 +71,8 @@ def traffic_entry(kernel_key: str):
     ent = data.get("kernels", {}).get(kernel_key)
     if not ent:
         return None
-    return ent["fetch_bytes"] * data["copy_scale_fetch"] + ent["write_bytes"] * data["copy_scale_write"]
+    sc = data["copy_scale"][kernel_key.rsplit("/", 1)[1]]
+    return ent["fetch_bytes"] * sc["fetch"] + ent["write_bytes"] * sc["write"]
 
 
 def step_kernel_name(storage: str, wl) -> str:
@@ -86,116 +87,221 @@ def step_kernel_name(storage: str, wl) -> str:
     return "k_collide_advect"
 
 
-# rocprofv3 commands whose outputs write_profiles() summarises (run from the repository root on the GPU)
+# rocprofv3 commands whose outputs write_profiles() summarises (run from the repository root on the GPU;
+# the trace run's stdout, the bench line, goes to gpurun_out/prof_trace.json)
+PROFILE_STORAGES = ("f32_dev", "f64", "bf16_dev")
+ADJ_GRIDS = (256, 1024)
+_STEP_ARGS = "--steps 20 --warmup 2 --modes none --no-adjoint --no-cpu-baseline --no-shock-vortex"
+VALU_COUNTERS = ("SQ_INSTS_VALU SQ_WAVES SQ_INSTS_SALU SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_ACTIVE_INST_VALU "
+                 "SQ_BUSY_CYCLES GRBM_GUI_ACTIVE")
 PROFILE_COMMANDS = {
     "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_trace -o trace -- "
              "python bench.py",
-    "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_fetch -o pmc -- "
-             "python bench.py --steps 20 --warmup 2 --modes none --no-adjoint --no-cpu-baseline",
-    "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_write -o pmc -- "
-             "python bench.py --steps 20 --warmup 2 --modes none --no-adjoint --no-cpu-baseline",
+    **{f"{c}_{st}": f"rocprofv3 --pmc {ctr} --output-format csv -d gpurun_out/prof_{c}_{st} -o pmc -- "
+                    f"python bench.py --storage {st} {_STEP_ARGS}"
+       for st in PROFILE_STORAGES for c, ctr in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE"),
+                                                 ("valu", VALU_COUNTERS))},
+    **{f"adj{n}_trace": f"rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_adj{n}_trace "
+                        f"-o trace -- python bench.py --adjoint-kernels {n}" for n in ADJ_GRIDS},
+    **{f"adj{n}_{c}": f"rocprofv3 --pmc {ctr} --output-format csv -d gpurun_out/prof_adj{n}_{c} -o pmc -- "
+                      f"python bench.py --adjoint-kernels {n} --reps 5"
+       for n in ADJ_GRIDS for c, ctr in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE"), ("valu", VALU_COUNTERS))},
 }
+SIMDS, CLOCK_GHZ = 1024, 2.4  # MI355X: 256 CUs x 4 SIMDs; peak engine clock
 
 
-def write_profiles(trace_dir: str, fetch_csv: str, write_csv: str, bench_json: str, workload: str,
-                   storage: str) -> None:
-    """Summaries of the three PROFILE_COMMANDS runs under profiles/ (host only, no GPU).
-
-    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are calibrated against the
-    streaming probes that bench.py runs (stream_ceiling: every dispatch reads
-    or writes 4 GiB, or both): scale = known bytes / counter bytes.
-    """
+def _pmc_rows(path):
     import csv
+
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _short(name: str) -> str:
+    """Kernel instance name without namespaces and argument list."""
+    return name.split("(")[0].replace("void ", "").replace("dvbm::", "")
+
+
+def _counter_by_dispatch(rows, counter):
+    """{(instance, grid): [value per dispatch]} of one counter (values summed over the device)."""
+    out = {}
+    for r in rows:
+        if r["Counter_Name"] == counter:
+            out.setdefault((_short(r["Kernel_Name"]), int(r["Grid_Size"])), []).append(float(r["Counter_Value"]))
+    return out
+
+
+def _copy_scale(rows, counter):
+    """Bytes per counter unit: the probe dispatches that move 4 GiB this way against the counter (KiB)."""
     import statistics
 
-    with open(bench_json) as fh:
+    probes = [float(r["Counter_Value"]) * 1024.0 for r in rows
+              if r["Counter_Name"] == counter and "k_stream<" in r["Kernel_Name"]]
+    big = [v for v in probes if v >= 0.5 * max(probes)]
+    return float(4 << 30) / statistics.median(big), len(big)
+
+
+def _trace_by_grid(path):
+    """{(instance, grid): [duration ns]} from a rocprofv3 kernel trace."""
+    import csv
+    import gzip
+
+    out = {}
+    with (gzip.open(path + ".gz", "rt") if not os.path.exists(path) else open(path)) as fh:
+        for r in csv.DictReader(fh):
+            g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"] or 1) * int(r["Grid_Size_Z"] or 1)
+            out.setdefault((_short(r["Kernel_Name"]), g), []).append(
+                int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return out
+
+
+def _valu_table(rows, durations, keys):
+    """Markdown rows: per-wave VALU / SALU / VMEM instructions, and VALU issue time per SIMD (instructions x
+    4 cycles, spread evenly over the SIMDs at the peak clock) against the kernel's traced duration."""
+    import statistics
+
+    ctr = {c: _counter_by_dispatch(rows, c) for c in ("SQ_INSTS_VALU", "SQ_WAVES", "SQ_INSTS_SALU",
+                                                          "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",
+                                                          "SQ_ACTIVE_INST_VALU", "GRBM_GUI_ACTIVE")}
+    lines = []
+    for k in keys:
+        if k not in ctr["SQ_INSTS_VALU"]:
+            continue
+        med = {c: statistics.median(v[k]) for c, v in ctr.items() if k in v}
+        waves = med["SQ_WAVES"]
+        valu_us = med["SQ_INSTS_VALU"] * 4 / SIMDS / (CLOCK_GHZ * 1e3)
+        dur_us = statistics.mean(durations[k]) / 1e3 if k in durations else float("nan")
+        # SQ_ACTIVE_INST_VALU counts quad-cycles; GRBM_GUI_ACTIVE sums the 8 XCDs' busy cycles
+        busy = (med["SQ_ACTIVE_INST_VALU"] * 4 / SIMDS) / (med["GRBM_GUI_ACTIVE"] / 8)
+        lines.append(f"| `{k[0][:70]}` | {k[1]} | {waves:.0f} | {med['SQ_INSTS_VALU'] / waves:.0f} | "
+                     f"{med['SQ_INSTS_SALU'] / waves:.0f} | "
+                     f"{(med['SQ_INSTS_VMEM_RD'] + med['SQ_INSTS_VMEM_WR']) / waves:.0f} | {valu_us:.1f} | "
+                     f"{dur_us:.1f} | {valu_us / dur_us:.2f} | {busy:.2f} |")
+    head = ("| kernel | grid (threads) | waves | VALU / wave | SALU / wave | VMEM / wave | VALU issue per SIMD (us) "
+            "| duration (us) | issue / duration | SQ_ACTIVE_INST_VALU busy |\n|---|---|---|---|---|---|---|---|---|---|\n")
+    return head + "\n".join(lines) + "\n"
+
+
+def write_profiles(run_dir: str, workload: str) -> None:
+    """Summaries under profiles/ of the PROFILE_COMMANDS runs, whose outputs are in run_dir (host only).
+
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are calibrated against the streaming probes that every
+    profiled run makes (stream_ceiling: each dispatch reads or writes 4 GiB, or both): scale = known
+    bytes / counter bytes.  Kernel durations come from the kernel traces, split by launch grid."""
+    import statistics
+
+    with open(os.path.join(run_dir, "prof_trace.json")) as fh:
         line = json.loads([ln for ln in fh if ln.startswith("{")][-1])
     kname = line["roofline"]["kernel"]
-
-    def per_kernel(path, counter):
-        vals, copies = [], []
-        with open(path) as fh:
-            for r in csv.DictReader(fh):
-                if r["Counter_Name"] != counter:
-                    continue
-                v = float(r["Counter_Value"]) * 1024.0
-                if kname + "<" in r["Kernel_Name"]:
-                    vals.append(v)
-                elif "k_stream<" in r["Kernel_Name"]:
-                    copies.append(v)
-        big = [v for v in copies if v >= 0.5 * max(copies)]  # the probes that move 4 GiB this way
-        return statistics.median(vals), statistics.median(big), len(vals), len(big)
-
-    fetch, fcopy, nf, ncf = per_kernel(fetch_csv, "FETCH_SIZE")
-    write, wcopy, nw, ncw = per_kernel(write_csv, "WRITE_SIZE")
-    copy_bytes = float(4 << 30)
-    sf, sw = copy_bytes / fcopy, copy_bytes / wcopy
     cells = line["config"]["nx"] * line["config"]["ny"]
-    alg = line["roofline"]["bytes_per_update"] * cells
-    with open(os.path.join(trace_dir, "trace_kernel_stats.csv")) as fh:
-        stats = list(csv.DictReader(fh))
-    # per-dispatch durations of the step kernel at the bench workload's grid (the largest grid it was
-    # launched with: the adjoint measurement launches the same kernel on a small grid)
-    store = {"f64": "StoreF64", "f32": "StoreF32", "bf16_dev": "StoreBF16", "fp16_dev": "StoreF16",
-             "f32_dev": "StoreF32Dev"}[storage]
-    inst = f"{kname}<{line['config']['split']}, dvbm::{store},"
-    durs = {}
-    with open(os.path.join(trace_dir, "trace_kernel_trace.csv")) as fh:
-        for r in csv.DictReader(fh):
-            if inst in r["Kernel_Name"]:
-                g = int(r["Grid_Size_X"])
-                durs.setdefault(g, []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
-    gmax = max(durs)
-    avg_ns = sum(durs[gmax]) / len(durs[gmax])
-    key = f"collide_advect/{workload}/{storage}"
+    trace = _trace_by_grid(os.path.join(run_dir, "prof_trace", "trace_kernel_trace.csv"))
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    tpath = os.path.join(ROOT, "profiles", "traffic.json")
-    data = {}
-    if os.path.exists(tpath):
-        with open(tpath) as fh:
-            data = json.load(fh)
-    if data.get("source_hash") != source_hash():
-        data = {"kernels": {}}
-    data.update({"source_hash": source_hash(), "copy_scale_fetch": sf, "copy_scale_write": sw})
-    data["kernels"][key] = {"fetch_bytes": fetch, "write_bytes": write, "kernel": kname}
-    with open(tpath, "w") as fh:
+    store = {"f64": "StoreF64", "f32": "StoreF32", "bf16_dev": "StoreBF16", "fp16_dev": "StoreF16",
+             "f32_dev": "StoreF32Dev"}
+    data = {"kernels": {}, "source_hash": source_hash()}
+
+    # ---- kernel trace of the default bench run, by instance and grid
+    name = f"kernel_trace_{workload}"
+    with open(os.path.join(ROOT, "profiles", f"{name}.md"), "w") as fh:
+        fh.write(f"# Kernel trace of the default bench run ({workload} and the bench's other workloads)\n\n")
+        fh.write(f"Command (repository root, one MI355X):\n\n    {PROFILE_COMMANDS['trace']} "
+                 f"> gpurun_out/prof_trace.json\n\n")
+        fh.write("Launches of the library's kernels, split by launch grid (threads), the 14 largest by total "
+                 "time:\n\n| kernel | grid (threads) | calls | average us | total ms |\n|---|---|---|---|---|\n")
+        lib = {k: v for k, v in trace.items() if k[0].startswith(("k_", "dvbm"))}
+        for k in sorted(lib, key=lambda k: -sum(lib[k]))[:14]:
+            v = lib[k]
+            fh.write(f"| `{k[0][:80]}` | {k[1]} | {len(v)} | {statistics.mean(v) / 1e3:.1f} | {sum(v) / 1e6:.1f} |\n")
+        inst = f"{kname}<{line['config']['split']}, {store[line['config']['storage']]},"
+        keys = [k for k in trace if k[0].startswith(inst)]
+        kmax = max(keys, key=lambda k: k[1])
+        avg_ns = statistics.mean(trace[kmax])
+        ms_ev = line["ms_per_step"]
+        alg = line["roofline"]["bytes_per_update"] * cells
+        fh.write(f"\nHeadline check: the {len(trace[kmax])} launches of `{kmax[0]}` on the "
+                 f"{line['config']['nx']} x {line['config']['ny']} grid ({kmax[1]} threads) average {avg_ns:.0f} ns; "
+                 f"the bench line of the same run times a launch at {ms_ev * 1e6:.0f} ns with HIP events on the "
+                 f"solver stream ({100 * (avg_ns / (ms_ev * 1e6) - 1):+.2f} %). Algorithmic bytes per launch "
+                 f"{alg / 1e9:.3f} GB -> {alg / avg_ns:.0f} GB/s by the trace, {line['roofline']['achieved']} GB/s "
+                 f"by the events ({line['value']} MLUPS).\n")
+
+    # ---- per storage: calibrated HBM traffic and VALU issue of the step kernel on the workload's grid
+    for st in PROFILE_STORAGES:
+        fr = _pmc_rows(os.path.join(run_dir, f"prof_fetch_{st}", "pmc_counter_collection.csv"))
+        wr = _pmc_rows(os.path.join(run_dir, f"prof_write_{st}", "pmc_counter_collection.csv"))
+        vr = _pmc_rows(os.path.join(run_dir, f"prof_valu_{st}", "pmc_counter_collection.csv"))
+        sf, nsf = _copy_scale(fr, "FETCH_SIZE")
+        sw, nsw = _copy_scale(wr, "WRITE_SIZE")
+        inst = f"{kname}<{line['config']['split']}, {store[st]},"
+        fd = {k: v for k, v in _counter_by_dispatch(fr, "FETCH_SIZE").items() if k[0].startswith(inst)}
+        wd = {k: v for k, v in _counter_by_dispatch(wr, "WRITE_SIZE").items() if k[0].startswith(inst)}
+        k = max(fd, key=lambda k: k[1])
+        fetch, write = statistics.median(fd[k]) * 1024.0, statistics.median(wd[k]) * 1024.0
+        alg = 2 * 2 * 25 * STORAGE_BYTES[st] * cells
+        data["kernels"][f"collide_advect/{workload}/{st}"] = {"fetch_bytes": fetch, "write_bytes": write,
+                                                              "kernel": kname}
+        data.setdefault("copy_scale", {})[st] = {"fetch": sf, "write": sw}
+        tk = [t for t in trace if t[0].startswith(inst)]
+        tk = max(tk, key=lambda t: t[1]) if tk else None
+        dur = statistics.mean(trace[tk]) if tk else float("nan")
+        tot = fetch * sf + write * sw
+        with open(os.path.join(ROOT, "profiles", f"{kname}_{workload}_{st}_counters.md"), "w") as fh:
+            fh.write(f"# {kname}: HBM traffic and instruction issue, {workload}, {st} storage\n\n")
+            fh.write("Commands (repository root, one MI355X):\n\n")
+            for c in ("fetch", "write", "valu"):
+                fh.write(f"    {PROFILE_COMMANDS[f'{c}_{st}']}\n")
+            fh.write(f"\nKernel duration from `{PROFILE_COMMANDS['trace']}` (the {st} launches on the full grid).\n\n")
+            fh.write("| counter | kernel, per dispatch (median) | calibration (4 GiB probes) | scaled bytes | "
+                     "algorithmic |\n|---|---|---|---|---|\n")
+            fh.write(f"| FETCH_SIZE | {fetch / 1024:.0f} KiB ({len(fd[k])} dispatches) | x{sf:.3f} ({nsf} probes) | "
+                     f"{fetch * sf / 1e9:.3f} GB | {alg / 2e9:.3f} GB read |\n")
+            fh.write(f"| WRITE_SIZE | {write / 1024:.0f} KiB ({len(wd[k])} dispatches) | x{sw:.3f} ({nsw} probes) | "
+                     f"{write * sw / 1e9:.3f} GB | {alg / 2e9:.3f} GB written |\n")
+            fh.write(f"\nMeasured traffic per launch {tot / 1e9:.3f} GB = {tot / alg:.3f} x the algorithmic "
+                     f"{alg / 1e9:.3f} GB (one read and one write of the 2Q populations of every cell); "
+                     f"over the traced duration {dur / 1e3:.0f} us: {tot / dur:.0f} GB/s moved, "
+                     f"{alg / dur:.0f} GB/s algorithmic.\n\n")
+            vk = [t for t in _counter_by_dispatch(vr, "SQ_INSTS_VALU") if t[0].startswith(inst)]
+            fh.write("Instruction issue (VALU issue per SIMD = VALU instructions x 4 cycles / 1024 SIMDs at "
+                     f"{CLOCK_GHZ} GHz, the share of the duration the SIMDs would need for VALU issue alone):\n\n")
+            fh.write(_valu_table(vr, {t: trace[tk] for t in vk} if tk else {}, vk))
+
+    # ---- the adjoint kernels (and the forward step they are compared with) at 256^2 and 1024^2
+    with open(os.path.join(ROOT, "profiles", "adjoint_kernels_256_1024.md"), "w") as fh:
+        fh.write("# Adjoint and forward step kernels, 256^2 and 1024^2 periodic (smooth random T)\n\n")
+        fh.write("Commands (repository root, one MI355X):\n\n")
+        for n in ADJ_GRIDS:
+            for c in ("trace", "fetch", "write", "valu"):
+                fh.write(f"    {PROFILE_COMMANDS[f'adj{n}_{c}']}\n")
+        fh.write("\nDurations from the traces; HBM bytes per cell from FETCH_SIZE and WRITE_SIZE calibrated on the "
+                 "4 GiB probes of the same run. Instances: split II; storage F64 / F32 / F32-dev; the last template "
+                 "argument of the adjoint kernels is the cotangent type.\n")
+        for n in ADJ_GRIDS:
+            at = _trace_by_grid(os.path.join(run_dir, f"prof_adj{n}_trace", "trace_kernel_trace.csv"))
+            fr = _pmc_rows(os.path.join(run_dir, f"prof_adj{n}_fetch", "pmc_counter_collection.csv"))
+            wr = _pmc_rows(os.path.join(run_dir, f"prof_adj{n}_write", "pmc_counter_collection.csv"))
+            vr = _pmc_rows(os.path.join(run_dir, f"prof_adj{n}_valu", "pmc_counter_collection.csv"))
+            sf, _ = _copy_scale(fr, "FETCH_SIZE")
+            sw, _ = _copy_scale(wr, "WRITE_SIZE")
+            fd, wd = _counter_by_dispatch(fr, "FETCH_SIZE"), _counter_by_dispatch(wr, "WRITE_SIZE")
+            keys = sorted(k for k in at if k[0].startswith(("k_adjoint_relax", "k_adjoint_flux", "k_collide_advect")))
+            cells = n * n
+            fh.write(f"\n## {n} x {n} (calibration x{sf:.3f} fetch, x{sw:.3f} write)\n\n"
+                     "| kernel | grid (threads) | calls | average us | read B/cell | written B/cell | GB/s |\n"
+                     "|---|---|---|---|---|---|---|\n")
+            for k in keys:
+                us = statistics.mean(at[k]) / 1e3
+                rb = statistics.median(fd[k]) * 1024.0 * sf / cells if k in fd else float("nan")
+                wb = statistics.median(wd[k]) * 1024.0 * sw / cells if k in wd else float("nan")
+                fh.write(f"| `{k[0][:78]}` | {k[1]} | {len(at[k])} | {us:.1f} | {rb:.0f} | {wb:.0f} | "
+                         f"{(rb + wb) * cells / (us * 1e3):.0f} |\n")
+            fh.write("\nInstruction issue (as in the step kernels' counter summaries):\n\n")
+            vk = [k for k in keys if k in _counter_by_dispatch(vr, "SQ_INSTS_VALU")]
+            fh.write(_valu_table(vr, {k: at[k] for k in vk}, vk))
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
         json.dump(data, fh, indent=1)
         fh.write("\n")
-    name = f"{kname}_{workload}_{storage}"
-    rows = sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:8]
-    with open(os.path.join(ROOT, "profiles", f"{name}_kernel_trace.md"), "w") as fh:
-        fh.write(f"# {kname}: kernel trace, {workload}, {storage} storage\n\n")
-        fh.write(f"Command (repository root, one MI355X):\n\n    {PROFILE_COMMANDS['trace']}\n\n")
-        fh.write("| kernel | calls | average ns | total ns |\n|---|---|---|---|\n")
-        for r in rows:
-            fh.write(f"| `{r['Name'][:110]}` | {r['Calls']} | {float(r['AverageNs']):.0f} | {r['TotalDurationNs']} |\n")
-        ms_ev = line["ms_per_step"]
-        other = sorted(g for g in durs if g != gmax)
-        note = (f" (the same instance was also launched with grids of {', '.join(map(str, other))} threads)"
-                if other else "")
-        fh.write(f"\nThe table averages every launch of a kernel instance{note}. The {len(durs[gmax])} launches "
-                 f"of {kname} on the "
-                 f"{line['config']['nx']} x {line['config']['ny']} grid ({gmax} threads) average {avg_ns:.0f} ns; "
-                 f"the bench line of the same run times it at {ms_ev * 1e6:.0f} ns per launch with HIP events "
-                 f"on the solver stream ("
-                 f"{100 * (avg_ns / (ms_ev * 1e6) - 1):+.2f} %). Algorithmic bytes per launch "
-                 f"{alg / 1e9:.3f} GB -> {alg / avg_ns:.0f} GB/s by the trace average, "
-                 f"{line['roofline']['achieved']} GB/s by the events.\n")
-    with open(os.path.join(ROOT, "profiles", f"{name}_hbm_traffic.md"), "w") as fh:
-        fh.write(f"# {kname}: HBM traffic, {workload}, {storage} storage\n\n")
-        fh.write("Commands (repository root, one MI355X):\n\n")
-        fh.write(f"    {PROFILE_COMMANDS['fetch']}\n    {PROFILE_COMMANDS['write']}\n\n")
-        fh.write("| counter | kernel, per dispatch (median) | copy calibration | scaled bytes | algorithmic |\n")
-        fh.write("|---|---|---|---|---|\n")
-        fh.write(f"| FETCH_SIZE | {fetch / 1024:.0f} KiB ({nf} dispatches) | 4 GiB probe reads {fcopy / 1024:.0f} KiB "
-                 f"-> x{sf:.3f} | {fetch * sf / 1e9:.3f} GB | {alg / 2e9:.3f} GB read |\n")
-        fh.write(f"| WRITE_SIZE | {write / 1024:.0f} KiB ({nw} dispatches) | 4 GiB probe writes {wcopy / 1024:.0f} KiB "
-                 f"-> x{sw:.3f} | {write * sw / 1e9:.3f} GB | {alg / 2e9:.3f} GB written |\n")
-        tot = fetch * sf + write * sw
-        fh.write(f"\nMeasured traffic per launch {tot / 1e9:.3f} GB = {tot / alg:.3f} x the algorithmic "
-                 f"{alg / 1e9:.3f} GB (one read and one write of the 2Q populations of every cell).\n")
-    print(f"profiles written for {key}: trace {avg_ns:.0f} ns, traffic {tot / 1e9:.3f} GB "
-          f"(fetch x{sf:.3f}, write x{sw:.3f})")
+    print("profiles written:", ", ".join(sorted(data["kernels"])))
 
 
 def wave_amplitude(T):
@@ -385,7 +491,7 @@ def adjoint_cost(device, n=256, nsteps=200, storages=("f64", "f32", "f32_dev"), 
         return (time.perf_counter() - t0) / reps
 
     res = {"workload": f"gaussian bump {n}x{n} periodic, {nsteps} steps, dt 1e-4", "storages": {}}
-    grads = {}
+    grads, grads32 = {}, {}
     # one target for every storage: the float64 run from the hidden bump
     tgt = rollout_temperature(torch.tensor(bump.T, device=device), torch.tensor(tau0, dtype=torch.float64),
                               torch.tensor(Pr, dtype=torch.float64), ones, zeros, zeros, nsteps, K=50,
@@ -415,24 +521,79 @@ def adjoint_cost(device, n=256, nsteps=200, storages=("f64", "f32", "f32_dev"), 
             r[f"K{K}_ratio"] = timed(lambda: with_gradient(K)) / t_fwd
             r[f"K{K}_f32_cotangent_ratio"] = timed(lambda: with_gradient(K, "f32")) / t_fwd
         grads[storage] = with_gradient(Ks[0])
-        g32 = with_gradient(Ks[0], "f32")
+        grads32[storage] = g32 = with_gradient(Ks[0], "f32")
         r["f32_cotangent_rel_err"] = float(torch.linalg.vector_norm(g32[0] - grads[storage][0])
                                            / torch.linalg.vector_norm(grads[storage][0]))
         res["storages"][storage] = r
     g64 = grads["f64"]
-    for storage in storages:
-        g = grads[storage]
-        res["storages"][storage]["gradient_rel_err_vs_f64"] = {
-            "T0": float(torch.linalg.vector_norm(g[0] - g64[0]) / torch.linalg.vector_norm(g64[0])),
-            "tau_ref": float(abs(g[1] - g64[1]) / abs(g64[1])), "Pr": float(abs(g[2] - g64[2]) / abs(g64[2]))}
+
+    def errs(g):
+        return {"T0": float(torch.linalg.vector_norm(g[0] - g64[0]) / torch.linalg.vector_norm(g64[0])),
+                "tau_ref": float(abs(g[1] - g64[1]) / abs(g64[1])), "Pr": float(abs(g[2] - g64[2]) / abs(g64[2]))}
+
     for storage in storages:
         r = res["storages"][storage]
+        r["gradient_rel_err_vs_f64"] = errs(grads[storage])
+        r["f32_cotangent_gradient_rel_err_vs_f64"] = errs(grads32[storage])
         r[f"K{Ks[0]}_gradient_s"] = r[f"K{Ks[0]}_ratio"] * r["forward_s"]
-    ok = [st for st in storages if max(res["storages"][st]["gradient_rel_err_vs_f64"].values()) <= 1e-5]
-    best = min(ok, key=lambda st: res["storages"][st][f"K{Ks[0]}_ratio"])
-    res["at_1e-5"] = {"storage": best, **{f"K{K}_ratio": res["storages"][best][f"K{K}_ratio"] for K in Ks},
-                      "storages_within_1e-5": ok}
+    # every (storage, cotangent) pair whose gradient is within 1e-5 of the float64 one; the headline
+    # ratio is the lowest among them
+    ok = [(st, cot) for st in storages for cot in ("f64", "f32")
+          if max(res["storages"][st]["gradient_rel_err_vs_f64" if cot == "f64"
+                                     else "f32_cotangent_gradient_rel_err_vs_f64"].values()) <= 1e-5]
+
+    def ratio(st, cot, K):
+        return res["storages"][st][f"K{K}_ratio" if cot == "f64" else f"K{K}_f32_cotangent_ratio"]
+
+    best = min(ok, key=lambda sc: ratio(*sc, Ks[0]))
+    res["at_1e-5"] = {"storage": best[0], "cotangent": best[1],
+                      **{f"K{K}_ratio": ratio(*best, K) for K in Ks},
+                      "within_1e-5": [f"{st}/{cot}" for st, cot in ok]}
     return res
+
+
+def adjoint_kernels(device, n, reps):
+    """Per-step times (HIP events on the solver stream) of the forward step and of the adjoint step with
+    float64 and float32 cotangents, for the F64, F32 and F32-dev storages on an n x n periodic grid with a
+    smooth random temperature (split II, tau_ref 2e-3, Pr 0.71, dt 1e-4): the kernels whose costs make up
+    the gradient/forward ratio, for profiling them by launch."""
+    import numpy as np
+    import torch
+
+    from paper_2510_04197_amd import Solver, make_params
+    from synth import smooth_random
+
+    T0 = smooth_random(n, n, seed=13, amp_rho=0.0, amp_u=0.0, amp_T=0.05, mean_u=(0.0, 0.0)).T
+    ones, zeros = np.ones((n, n)), np.zeros((n, n))
+    out = {"grid": n, "reps": reps, "storages": {}}
+    for st in ("f64", "f32", "f32_dev"):
+        p = make_params(n, n, dx=1.0 / n, dy=1.0 / n, split=2, storage=st, tau_ref=2e-3, Pr=0.71, dt=1e-4)
+        s = Solver(p, ones, zeros, zeros, T0, device=device)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.step(2)
+        e0.record(s.stream)
+        s.step(reps)
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        r = {"forward_us": e0.elapsed_time(e1) / reps * 1e3}
+        state = s.state_buffer.clone()
+        gen = torch.Generator(device=device).manual_seed(17)
+        for dt in (torch.float64, torch.float32):
+            lam = s.new_cotangent(dt)
+            lam.copy_(torch.randn(lam.shape, generator=gen, device=device, dtype=torch.float64))
+            lam2 = torch.empty_like(lam)
+            dp = torch.zeros(2, dtype=torch.float64, device=device)
+            s.adjoint_step(state, lam, lam2, dp)
+            e0.record(s.stream)
+            for _ in range(reps):
+                s.adjoint_step(state, lam, lam2, dp)
+            e1.record(s.stream)
+            torch.cuda.synchronize()
+            r[f"adjoint_us_{'f64' if dt == torch.float64 else 'f32'}_cotangent"] = e0.elapsed_time(e1) / reps * 1e3
+        out["storages"][st] = r
+        s.close()
+        torch.cuda.empty_cache()
+    return out
 
 
 def stream_ceiling(device, nbytes=4 << 30, reps=5):
@@ -526,12 +687,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
     ap.add_argument("--no-shock-vortex", action="store_true", help="skip the 2048x1024 shock-vortex runs")
-    ap.add_argument("--write-profiles", nargs=4, metavar=("TRACE_DIR", "FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
-                    help="host only: summarise the rocprofv3 runs of PROFILE_COMMANDS into profiles/")
+    ap.add_argument("--adjoint-kernels", type=int, metavar="N",
+                    help="only time the forward and adjoint step kernels on an N x N grid (for profiling)")
+    ap.add_argument("--reps", type=int, default=50, help="launches per kernel timed by --adjoint-kernels")
+    ap.add_argument("--write-profiles", metavar="RUN_DIR",
+                    help="host only: summarise the rocprofv3 runs of PROFILE_COMMANDS (outputs in RUN_DIR) into "
+                         "profiles/")
     args = ap.parse_args()
 
     if args.write_profiles:
-        write_profiles(*args.write_profiles, workload=args.workload, storage=args.storage)
+        write_profiles(args.write_profiles, workload=args.workload)
         return
 
     if args.gpus != 1:
@@ -544,6 +709,11 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     device = "cuda:0"
+    if args.adjoint_kernels:
+        res = adjoint_kernels(device, args.adjoint_kernels, args.reps)
+        res["stream_probe_GBps"] = stream_ceiling(device)  # the counter calibration of a profiled run
+        print(json.dumps({"adjoint_kernels": res}))
+        return
     print(f"[bench] workload {args.workload}, storage {args.storage}, steps {args.steps}, warmup {args.warmup}",
           file=sys.stderr, flush=True)
     wl, phys = workload_fields(args.workload)
