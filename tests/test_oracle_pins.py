@@ -738,7 +738,7 @@ def test_pressure_front_speed_at_mach_2():
     a right-running drop of 5e-7 with a plateau between them; each front is
     located where (p - 1) / 1e-6 falls through its mid level (0.75, 0.25), at
     1/3 and at the end of 0.15 / c, and c = (v_+ - v_-) / 2, u = (v_+ + v_-) / 2
-    match sqrt(gamma R T) and the flow within 3 %."""
+    match sqrt(gamma R T) and the flow within 1 % (measured 0.41 % and 0.26 %)."""
     n, ny, amp, gamma, mach = 128, 4, 1e-6, 4.0 / 3.0, 2.0
     dx = 1.0 / n
     x = (np.arange(n) + 0.5) * dx
@@ -773,4 +773,5 @@ def test_pressure_front_speed_at_mach_2():
     r2, l2 = fronts(f, g, n_end * dt)
     vr, vl = (r2 - r1) / ((n_end - n_mid) * dt), (l2 - l1) / ((n_end - n_mid) * dt)
     c, u = 0.5 * (vr - vl), 0.5 * (vr + vl)
-    assert abs(c / c0 - 1) < 3e-2 and abs(u / U - 1) < 3e-2, (c / c0, u / U)
+    print(f"[oracle pressure front] 128 cells, Mach 2: c / c0 - 1 = {c / c0 - 1:.2e}, u / U - 1 = {u / U - 1:.2e}")
+    assert abs(c / c0 - 1) < 1e-2 and abs(u / U - 1) < 1e-2, (c / c0, u / U)
