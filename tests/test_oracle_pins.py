@@ -775,3 +775,24 @@ def test_pressure_front_speed_at_mach_2():
     c, u = 0.5 * (vr - vl), 0.5 * (vr + vl)
     print(f"[oracle pressure front] 128 cells, Mach 2: c / c0 - 1 = {c / c0 - 1:.2e}, u / U - 1 = {u / U - 1:.2e}")
     assert abs(c / c0 - 1) < 1e-2 and abs(u / U - 1) < 1e-2, (c / c0, u / U)
+
+
+def test_adjoint_windows_match_full_grid():
+    """The window form of the step's reverse mode (tests/adjoint_windows.py,
+    which the full-size GPU adjoint tests use) equals reverse mode through the
+    oracle's step on the whole periodic grid at the sampled cells, corners and
+    cells whose windows wrap included."""
+    from adjoint_windows import oracle_adjoint_windows
+    wl = smooth_random(17, 13, seed=2)
+    cfg = O.Config(nx=17, ny=13, split=2, dx=wl.dx, dy=wl.dy, Pr=0.5, tau_ref=0.02)
+    f0, g0 = O.initial_state(wl.rho, wl.ux, wl.uy, wl.T, cfg)
+    rng = np.random.default_rng(0)
+    X = torch.stack([f0, g0]) * (1 + 0.01 * torch.tensor(rng.standard_normal((2,) + tuple(f0.shape))))
+    lam1 = torch.tensor(rng.standard_normal(tuple(X.shape)))
+    Xr = X.clone().requires_grad_(True)
+    fn, gn = O.step(Xr[0], Xr[1], cfg, 3e-3)
+    ((lam1[0] * fn).sum() + (lam1[1] * gn).sum()).backward()
+    ys, xs = torch.tensor([0, 5, 12, 7, 0]), torch.tensor([0, 3, 16, 9, 16])
+    win = oracle_adjoint_windows(X, lam1, ys, xs, cfg, 3e-3)
+    ref = Xr.grad[:, :, ys, xs]
+    assert float((win - ref).abs().max() / ref.abs().max()) < 1e-14
