@@ -97,15 +97,20 @@ def test_step_adjoint_grid_shapes(shape, bc):
     check_step_adjoint(step_adjoint_vs_oracle(shape[0], shape[1], 2, 0.71, bc[0], bc[1], "f64", seed=3))
 
 
-@pytest.mark.parametrize("storage,nx,ny", (("f64", 4096, 4096), ("f32_dev", 4099, 2053)))
-def test_step_adjoint_full_size_sampled(storage, nx, ny):
+@pytest.mark.parametrize("storage,nx,ny,bc_x", (("f64", 4096, 4096, "periodic"), ("f32_dev", 4099, 2053, "periodic"),
+                                                 ("f32", 2048, 1024, "zero_gradient")))
+def test_step_adjoint_full_size_sampled(storage, nx, ny, bc_x):
     """One adjoint step on the 4096^2 grid of the precision workload (float64
-    storage) and on a ragged 4099 x 2053 grid (float32 deviations: 70 strips
-    of 58 columns and a 39-column tail), periodic, the state perturbed by 1 %
-    noise so the limiter takes every branch: lam at 36 sampled cells (corners
-    included) against the oracle's reverse mode on windows (1e-11)."""
+    storage), on a ragged 4099 x 2053 grid (float32 deviations: 70 strips of
+    58 columns and a 39-column tail) and on the 2048 x 1024 shock-vortex grid
+    with zero-gradient x (float32), the state perturbed by 1 % noise so the
+    limiter takes every branch: lam at 36 sampled cells against the oracle's
+    reverse mode on periodic windows (1e-11).  The periodic grids' samples
+    include the corners; with zero-gradient x the samples keep 4 cells from
+    the x edges, where a periodic window equals the domain (the edges' ghost
+    shares are checked element by element on the small grids)."""
     wl = thermal_wave(nx, seed=0) if nx == ny else smooth_random(nx, ny, seed=4)
-    p = make_params(wl.nx, wl.ny, dx=wl.dx, dy=wl.dy, split=2, storage=storage, Pr=0.5, tau_ref=2e-3)
+    p = make_params(wl.nx, wl.ny, dx=wl.dx, dy=wl.dy, split=2, storage=storage, Pr=0.5, tau_ref=2e-3, bc_x=bc_x)
     s = Solver(p, wl.rho, wl.ux, wl.uy, wl.T, device=DEV)
     gen = torch.Generator(device=DEV).manual_seed(3)
     X = s.store_populations()
@@ -117,12 +122,15 @@ def test_step_adjoint_full_size_sampled(storage, nx, ny):
     s.adjoint_step(s.state_buffer, lam1, lam0, None)
     rng = np.random.default_rng(7)
     ys = torch.tensor(np.concatenate([rng.integers(0, ny, 32), [0, ny - 1, 0, ny - 1]]))
-    xs = torch.tensor(np.concatenate([rng.integers(0, nx, 32), [0, nx - 1, nx - 1, 0]]))
+    if bc_x == "periodic":
+        xs = torch.tensor(np.concatenate([rng.integers(0, nx, 32), [0, nx - 1, nx - 1, 0]]))
+    else:
+        xs = torch.tensor(np.concatenate([rng.integers(4, nx - 4, 32), [4, nx - 5, nx - 5, 4]]))
     got = lam0[:, :, ys.to(DEV), xs.to(DEV)].cpu()
     ref = oracle_adjoint_windows(X, lam1, ys, xs, oracle_cfg(p), s.dt)
     s.close()
     e = rel(got, ref)
-    print(f"[adjoint {nx}x{ny} {storage}] sampled lam against the oracle: {e:.2e}", flush=True)
+    print(f"[adjoint {nx}x{ny} {storage} {bc_x}] sampled lam against the oracle: {e:.2e}", flush=True)
     assert e < 1e-11
 
 
