@@ -20,7 +20,9 @@
  * ---------------------------------------
  *  - All pointers named "device" are device (HBM) addresses on the current
  *    HIP device; they are owned by the caller.  The library never allocates
- *    or frees device memory.  Pointers named "host" are host addresses.
+ *    or frees device memory (the fixed scratch of dvbm_adjoint_step_noalloc
+ *    is a static device array of the loaded code object).  Pointers named
+ *    "host" are host addresses.
  *  - Macroscopic fields are dense row-major float64 arrays of ny*nx values,
  *    element (y, x) at index y*nx + x; cell (y, x) has its centre at
  *    ((x + 1/2) dx, (y + 1/2) dy).

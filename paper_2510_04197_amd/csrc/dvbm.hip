@@ -756,7 +756,7 @@ KParams make_kparams(const dvbm_params& p, double dt) {
 // CU at a time, so one round of ranges (as many workgroups as the device
 // holds) ends with its slowest CU; `rounds` rounds of shorter ranges let the
 // faster CUs take more of them.  Ranges keep at least 48 rows (the 4
-// warm-up rows of a range stay under 10 %), and never fewer ranges than one
+// stencil rows read beyond a range stay under 10 %), and never fewer ranges than one
 // round nor ranges shorter than 9 rows.  Measured on the 4096^2 thermal
 // wave: float64 storage gains 15 % at 6 rounds, float32 4.5 % at 4 rounds,
 // the 16-bit formats nothing.

@@ -1,13 +1,15 @@
 // Column-sweep form of the fused DDF-QE DVBM step (float32 arithmetic for
 // 32-bit and 16-bit storage, float64 for float64 storage).
 //
-// A workgroup of two waves owns a strip of SWEEP_OWN columns and walks a
-// range of rows in +y; one wave advances f, the other g.  The 64 lanes of a
-// wave hold the columns x0 - 2 .. x0 + 61: lanes 2 .. 61 own their cells,
-// the two lanes at each end only supply the x stencil of their neighbours.  The x neighbours of a population come from the adjacent lanes
-// (DPP wave shifts), the y neighbours from a window of rows kept in registers
-// per population plane, so every stored value is read from memory once per
-// strip (the 4 overlap columns and the 4 warm-up rows of a range aside).
+// A strip of SWEEP_OWN columns is advanced by two waves that walk a range of
+// rows in +y, one advancing f and the other g; a workgroup holds SWEEP_K
+// adjacent strips.  The 64 lanes of a wave hold the columns x0 - 2 .. x0 + 61:
+// lanes 2 .. 61 own their cells, the two lanes at each end only supply the x
+// stencil of their neighbours.  The x neighbours of a population come from
+// the adjacent lanes (DPP wave shifts), the y neighbours from a window of rows
+// kept in registers per population plane, so every stored value is read from
+// memory once per strip (the 4 overlap columns, and the 2 stencil rows below
+// and above each range of rows, aside).
 // While a row is being finished, each plane's next row is already in flight.
 #pragma once
 
