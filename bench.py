@@ -182,8 +182,8 @@ def _valu_table(rows, durations, keys):
     return head + "\n".join(lines) + "\n"
 
 
-def write_profiles(run_dir: str, workload: str) -> None:
-    """Summaries under profiles/ of the PROFILE_COMMANDS runs, whose outputs are in run_dir (host only).
+def write_profiles(run_dir: str, workload: str, out_dir: str = os.path.join(ROOT, "profiles")) -> None:
+    """Summaries in out_dir (profiles/) of the PROFILE_COMMANDS runs, whose outputs are in run_dir (host only).
 
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are calibrated against the streaming probes that every
     profiled run makes (stream_ceiling: each dispatch reads or writes 4 GiB, or both): scale = known
@@ -195,14 +195,14 @@ def write_profiles(run_dir: str, workload: str) -> None:
     kname = line["roofline"]["kernel"]
     cells = line["config"]["nx"] * line["config"]["ny"]
     trace = _trace_by_grid(os.path.join(run_dir, "prof_trace", "trace_kernel_trace.csv"))
-    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    os.makedirs(os.path.join(out_dir), exist_ok=True)
     store = {"f64": "StoreF64", "f32": "StoreF32", "bf16_dev": "StoreBF16", "fp16_dev": "StoreF16",
              "f32_dev": "StoreF32Dev"}
     data = {"kernels": {}, "source_hash": source_hash()}
 
     # ---- kernel trace of the default bench run, by instance and grid
     name = f"kernel_trace_{workload}"
-    with open(os.path.join(ROOT, "profiles", f"{name}.md"), "w") as fh:
+    with open(os.path.join(out_dir, f"{name}.md"), "w") as fh:
         fh.write(f"# Kernel trace of the default bench run ({workload} and the bench's other workloads)\n\n")
         fh.write(f"Command (repository root, one MI355X):\n\n    {PROFILE_COMMANDS['trace']} "
                  f"> gpurun_out/prof_trace.json\n\n")
@@ -245,7 +245,7 @@ def write_profiles(run_dir: str, workload: str) -> None:
         tk = max(tk, key=lambda t: t[1]) if tk else None
         dur = statistics.mean(trace[tk]) if tk else float("nan")
         tot = fetch * sf + write * sw
-        with open(os.path.join(ROOT, "profiles", f"{kname}_{workload}_{st}_counters.md"), "w") as fh:
+        with open(os.path.join(out_dir, f"{kname}_{workload}_{st}_counters.md"), "w") as fh:
             fh.write(f"# {kname}: HBM traffic and instruction issue, {workload}, {st} storage\n\n")
             fh.write("Commands (repository root, one MI355X):\n\n")
             for c in ("fetch", "write", "valu"):
@@ -267,7 +267,7 @@ def write_profiles(run_dir: str, workload: str) -> None:
             fh.write(_valu_table(vr, {t: trace[tk] for t in vk} if tk else {}, vk))
 
     # ---- the adjoint kernels (and the forward step they are compared with) at 256^2 and 1024^2
-    with open(os.path.join(ROOT, "profiles", "adjoint_kernels_256_1024.md"), "w") as fh:
+    with open(os.path.join(out_dir, "adjoint_kernels_256_1024.md"), "w") as fh:
         fh.write("# Adjoint and forward step kernels, 256^2 and 1024^2 periodic (smooth random T)\n\n")
         fh.write("Commands (repository root, one MI355X):\n\n")
         for n in ADJ_GRIDS:
@@ -298,7 +298,7 @@ def write_profiles(run_dir: str, workload: str) -> None:
             fh.write("\nInstruction issue (as in the step kernels' counter summaries):\n\n")
             vk = [k for k in keys if k in _counter_by_dispatch(vr, "SQ_INSTS_VALU")]
             fh.write(_valu_table(vr, {k: at[k] for k in vk}, vk))
-    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+    with open(os.path.join(out_dir, "traffic.json"), "w") as fh:
         json.dump(data, fh, indent=1)
         fh.write("\n")
     print("profiles written:", ", ".join(sorted(data["kernels"])))
