@@ -11,6 +11,7 @@ Tolerances (relative L2 over all populations of both distributions):
 
 import ctypes
 import math
+import os
 
 import numpy as np
 import pytest
@@ -364,6 +365,35 @@ def test_vortex_1024_sampled(storage, tol):
     s.step(2)
     got, ref, before = sampled_check(s, p)
     check_sampled(got, ref, before, storage, tol, "vortex 1024")
+
+
+def test_vortex_1024_300_steps_against_the_oracle():
+    """The 1024^2 Mach-1 vortex workload over 300 steps against the oracle's
+    own run of the same steps at full size (tests/golden/vortex_1024_oracle_300.npz,
+    written by tests/golden/make_vortex_reference.py from the oracle alone,
+    with the time step it used): rho and T on the 128^2 grid of 8 x 8 block
+    averages and at 256 sampled cells.  This ties the long runs, which compare
+    float32 storage with the float64-storage GPU run, to the oracle at the
+    workload's size: float64 storage within 1e-12, FP32 and FP32-dev within
+    2e-6 (both measured near 5e-7 at 300 steps against float64 storage)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "vortex_1024_oracle_300.npz")
+    ref = np.load(path)
+    ys, xs = torch.tensor(ref["ys"]), torch.tensor(ref["xs"])
+    wl = isentropic_vortex(1024, seed=0, mach_adv=1.0, mach_v=0.3, r_frac=0.05)
+    pool = torch.nn.functional.avg_pool2d
+    for storage, tol in (("f64", 1e-12), ("f32", 2e-6), ("f32_dev", 2e-6)):
+        s, _ = solver(wl, split=2, storage=storage, Pr=0.71, gamma=1.4, tau_ref=5e-5, dt=float(ref["dt"]))
+        s.step(int(ref["steps"]))
+        m = s.moments(fields=True, sums=False)
+        s.close()
+        errs = {}
+        for k in ("rho", "T"):
+            f = m[k]
+            errs[k + "_128"] = rel(pool(f[None, None], 8)[0, 0].cpu(), torch.tensor(ref[k + "_128"]))
+            errs[k + "_samples"] = rel(f[ys.to(f.device), xs.to(f.device)].cpu(), torch.tensor(ref[k + "_samples"]))
+        print(f"[vortex 1024, 300 steps, oracle] {storage}: " + ", ".join(f"{k} {v:.1e}" for k, v in errs.items()),
+              flush=True)
+        assert max(errs.values()) < tol, (storage, errs)
 
 
 @pytest.mark.parametrize("storage", ("f32", "f32_dev"))
