@@ -374,8 +374,9 @@ def test_vortex_1024_300_steps_against_the_oracle():
     with the time step it used): rho and T on the 128^2 grid of 8 x 8 block
     averages and at 256 sampled cells.  This ties the long runs, which compare
     float32 storage with the float64-storage GPU run, to the oracle at the
-    workload's size: float64 storage within 1e-12, FP32 and FP32-dev within
-    2e-6 (both measured near 5e-7 at 300 steps against float64 storage)."""
+    workload's size: float64 storage within 1e-12 (measured 0.8e-15 to
+    1.3e-15), FP32 and FP32-dev within 2e-6 (measured 3.1e-7 to 6.4e-7 and
+    1.9e-7 to 3.4e-7)."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "vortex_1024_oracle_300.npz")
     ref = np.load(path)
     ys, xs = torch.tensor(ref["ys"]), torch.tensor(ref["xs"])
