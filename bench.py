@@ -94,13 +94,14 @@ ADJ_GRIDS = (256, 1024)
 _STEP_ARGS = "--steps 20 --warmup 2 --modes none --no-adjoint --no-cpu-baseline --no-shock-vortex"
 VALU_COUNTERS = ("SQ_INSTS_VALU SQ_WAVES SQ_INSTS_SALU SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_ACTIVE_INST_VALU "
                  "SQ_BUSY_CYCLES GRBM_GUI_ACTIVE")
+STALL_COUNTERS = "SQ_WAIT_INST_ANY SQ_WAIT_ANY SQ_WAVE_CYCLES SQ_BUSY_CYCLES TCC_HIT_sum TCC_MISS_sum"
 PROFILE_COMMANDS = {
     "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_trace -o trace -- "
              "python bench.py",
     **{f"{c}_{st}": f"rocprofv3 --pmc {ctr} --output-format csv -d gpurun_out/prof_{c}_{st} -o pmc -- "
                     f"python bench.py --storage {st} {_STEP_ARGS}"
        for st in PROFILE_STORAGES for c, ctr in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE"),
-                                                 ("valu", VALU_COUNTERS))},
+                                                 ("valu", VALU_COUNTERS), ("stall", STALL_COUNTERS))},
     **{f"adj{n}_trace": f"rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_adj{n}_trace "
                         f"-o trace -- python bench.py --adjoint-kernels {n}" for n in ADJ_GRIDS},
     **{f"adj{n}_{c}": f"rocprofv3 --pmc {ctr} --output-format csv -d gpurun_out/prof_adj{n}_{c} -o pmc -- "
@@ -248,7 +249,7 @@ def write_profiles(run_dir: str, workload: str, out_dir: str = os.path.join(ROOT
         with open(os.path.join(out_dir, f"{kname}_{workload}_{st}_counters.md"), "w") as fh:
             fh.write(f"# {kname}: HBM traffic and instruction issue, {workload}, {st} storage\n\n")
             fh.write("Commands (repository root, one MI355X):\n\n")
-            for c in ("fetch", "write", "valu"):
+            for c in ("fetch", "write", "valu", "stall"):
                 fh.write(f"    {PROFILE_COMMANDS[f'{c}_{st}']}\n")
             fh.write(f"\nKernel duration from `{PROFILE_COMMANDS['trace']}` (the {st} launches on the full grid).\n\n")
             fh.write("| counter | kernel, per dispatch (median) | calibration (4 GiB probes) | scaled bytes | "
@@ -265,6 +266,18 @@ def write_profiles(run_dir: str, workload: str, out_dir: str = os.path.join(ROOT
             fh.write("Instruction issue (VALU issue per SIMD = VALU instructions x 4 cycles / 1024 SIMDs at "
                      f"{CLOCK_GHZ} GHz, the share of the duration the SIMDs would need for VALU issue alone):\n\n")
             fh.write(_valu_table(vr, {t: trace[tk] for t in vk} if tk else {}, vk))
+            sr = _pmc_rows(os.path.join(run_dir, f"prof_stall_{st}", "pmc_counter_collection.csv"))
+            sc = {c: _counter_by_dispatch(sr, c) for c in STALL_COUNTERS.split()}
+            sk = [t for t in sc["SQ_WAVE_CYCLES"] if t[0].startswith(inst)]
+            if sk:
+                t = max(sk, key=lambda t: t[1])
+                med = {c: statistics.median(v[t]) for c, v in sc.items() if t in v}
+                hit = med["TCC_HIT_sum"] / (med["TCC_HIT_sum"] + med["TCC_MISS_sum"])
+                fh.write(f"\nStalls and L2 (median over {len(sc['SQ_WAVE_CYCLES'][t])} dispatches): waves wait on a "
+                         f"dependency (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES) {med['SQ_WAIT_INST_ANY'] / med['SQ_WAVE_CYCLES']:.2f} "
+                         f"of their cycles and on anything, barriers included (SQ_WAIT_ANY / SQ_WAVE_CYCLES), "
+                         f"{med['SQ_WAIT_ANY'] / med['SQ_WAVE_CYCLES']:.2f}; L2 hit rate "
+                         f"TCC_HIT / (TCC_HIT + TCC_MISS) {hit:.3f}.\n")
 
     # ---- the adjoint kernels (and the forward step they are compared with) at 256^2 and 1024^2
     with open(os.path.join(out_dir, "adjoint_kernels_256_1024.md"), "w") as fh:

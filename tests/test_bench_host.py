@@ -57,6 +57,9 @@ def _run_dir(tmp):
              probe_write + [(STEP.format(store), 1000, "WRITE_SIZE", 1600.0)] * 5)
         _pmc(os.path.join(tmp, f"prof_valu_{st}", "pmc_counter_collection.csv"),
              [(STEP.format(store), 1000, c, v) for c, v in zip(VALU, (2.4e6, 100, 1e4, 5e3, 5e3, 1.2e6, 8e4))])
+        _pmc(os.path.join(tmp, f"prof_stall_{st}", "pmc_counter_collection.csv"),
+             [(STEP.format(store), 1000, c, v) for c, v in zip(bench.STALL_COUNTERS.split(),
+                                                               (4e5, 2e5, 1e6, 5e5, 900.0, 100.0))])
     for g in bench.ADJ_GRIDS:
         _trace(os.path.join(tmp, f"prof_adj{g}_trace", "trace_kernel_trace.csv"), [(k, 256, 500) for k in ADJ])
         _pmc(os.path.join(tmp, f"prof_adj{g}_fetch", "pmc_counter_collection.csv"),
@@ -90,6 +93,9 @@ def test_write_profiles_calibrates_against_the_probes(tmp_path):
     # VALU: 2.4e6 instructions over 100 waves; x 4 cycles / 1024 SIMDs / 2.4 GHz = 3.906 us in a 1 us
     # launch; SQ_ACTIVE_INST_VALU 1.2e6 quad-cycles / 1024 SIMDs over 8e4 / 8 cycles per XCD = 0.47
     assert "| 1000 | 100 | 24000 | 100 | 100 | 3.9 | 1.0 | 3.91 | 0.47 |" in text
+    # 4e5 / 1e6 wave cycles waiting on a dependency, 2e5 / 1e6 on anything; 900 L2 hits of 1000
+    assert "(SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES) 0.40" in text and "SQ_WAVE_CYCLES), 0.20" in text
+    assert "(TCC_HIT + TCC_MISS) 0.900" in text
     # the headline check uses the workload's grid only (1000 threads, 1000 ns) against the events' 1 us
     with open(os.path.join(out, "kernel_trace_thermal_wave_4096.md")) as fh:
         trace = fh.read()

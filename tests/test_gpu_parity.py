@@ -397,6 +397,38 @@ def test_vortex_1024_300_steps_against_the_oracle():
         assert max(errs.values()) < tol, (storage, errs)
 
 
+def test_shock_vortex_2048x1024_100_steps_against_the_oracle():
+    """The 2048 x 1024 shock-vortex workload (Pr 0.71, gamma 1.4, x
+    zero-gradient, y periodic) over 100 steps against the oracle's own
+    full-size run of the same steps (tests/golden/shock_vortex_2048x1024_oracle_100.npz,
+    written by tests/golden/make_shock_vortex_reference.py from the oracle
+    alone, with the time step it used): rho and T on the 128 x 64 grid of
+    16 x 16 block averages and at 256 sampled cells, the x edges included.
+    Float64 storage within 1e-12 (measured 2.4e-16 to 5.5e-16), FP32 and
+    FP32-dev within 2e-6 (measured 1.3e-7 to 2.4e-7 and 3.3e-7 to 7.6e-7:
+    at Mach 1.2 the deviations from the rest state are as large as the
+    values, so FP32-dev does not gain here)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "shock_vortex_2048x1024_oracle_100.npz")
+    ref = np.load(path)
+    ys, xs = torch.tensor(ref["ys"]), torch.tensor(ref["xs"])
+    wl = shock_vortex(2048, 1024, mach_s=1.2, mach_v=0.25, r_frac=0.075, gamma=1.4)
+    pool = torch.nn.functional.avg_pool2d
+    for storage, tol in (("f64", 1e-12), ("f32", 2e-6), ("f32_dev", 2e-6)):
+        s, _ = solver(wl, split=2, storage=storage, Pr=0.71, gamma=1.4, tau_ref=wl.phys["mu"], bc_x="zero_gradient",
+                      bc_y="periodic", dt=float(ref["dt"]))
+        s.step(int(ref["steps"]))
+        m = s.moments(fields=True, sums=False)
+        s.close()
+        errs = {}
+        for k in ("rho", "T"):
+            f = m[k]
+            errs[k + "_blocks"] = rel(pool(f[None, None], 16)[0, 0].cpu(), torch.tensor(ref[k + "_blocks"]))
+            errs[k + "_samples"] = rel(f[ys.to(f.device), xs.to(f.device)].cpu(), torch.tensor(ref[k + "_samples"]))
+        print(f"[shock-vortex 2048x1024, 100 steps, oracle] {storage}: "
+              + ", ".join(f"{k} {v:.1e}" for k, v in errs.items()), flush=True)
+        assert max(errs.values()) < tol, (storage, errs)
+
+
 @pytest.mark.parametrize("storage", ("f32", "f32_dev"))
 @pytest.mark.parametrize("Pr,gamma", [(Pr, g) for Pr in (0.1, 0.71, 2.0) for g in (1.4, 5.0 / 3.0)])
 def test_shock_vortex_2048x1024_sampled(Pr, gamma, storage):
