@@ -304,6 +304,59 @@ def _gradient(T0, ones, zeros, kw, tgt, K):
     return T0t.grad, taut.grad, prt.grad
 
 
+def test_rollout_gradient_matches_oracle_256():
+    """The gradient workload as specified (256^2 periodic, the hidden-bump
+    target, T0 = 1 plus a smooth mode, 200 steps at dt = 1e-4, FP64 storage),
+    checkpoints every 10 and every 50 steps: dL/dT0, dL/dtau_ref and dL/dPr
+    against reverse mode through the oracle's 200 steps (taken segment by
+    segment, 5 steps each, to bound its memory), within 1e-10."""
+    n, nsteps = FD_N, FD_STEPS
+    bump = gaussian_bump(n, seed=7, amp=0.1, width=0.1)
+    T0 = smooth_T0(n, seed=13)
+    ones, zeros = np.ones((n, n)), np.zeros((n, n))
+    kw = dict(dx=1.0 / n, dy=1.0 / n, split=2, storage="f64", dt=1e-4)
+    tgt = rollout_temperature(torch.tensor(bump.T, device=DEV), torch.tensor(FD_TAU, dtype=torch.float64),
+                              torch.tensor(FD_PR, dtype=torch.float64), ones, zeros, zeros, nsteps, K=10, **kw).detach()
+    grads = {}
+    for K in (10, 50):
+        T0t = torch.tensor(T0, device=DEV, requires_grad=True)
+        taut = torch.tensor(FD_TAU, dtype=torch.float64, requires_grad=True)
+        prt = torch.tensor(FD_PR, dtype=torch.float64, requires_grad=True)
+        out = rollout_temperature(T0t, taut, prt, ones, zeros, zeros, nsteps, K=K, **kw)
+        ((out - tgt) ** 2).sum().backward()
+        grads[K] = (T0t.grad.cpu(), float(taut.grad), float(prt.grad))
+    # the oracle's reverse mode, segment by segment: the forward keeps the states
+    # at segment boundaries, the reverse recomputes one segment at a time with its
+    # graph and pushes the cotangents through it, so at most one segment's graph
+    # (5 steps, about 12 GB at this size) is alive
+    seg = 5
+    cfg = O.Config(nx=n, ny=n, split=2, dx=1.0 / n, dy=1.0 / n, Pr=FD_PR, tau_ref=FD_TAU)
+    T0o = torch.tensor(T0, requires_grad=True)
+    tauo = torch.tensor(FD_TAU, dtype=torch.float64, requires_grad=True)
+    pro = torch.tensor(FD_PR, dtype=torch.float64, requires_grad=True)
+    f0, g0 = O.initial_state(ones, zeros, zeros, T0o, cfg)
+    states = [(f0.detach(), g0.detach())]
+    with torch.no_grad():
+        for _ in range(nsteps // seg):
+            states.append(O.run(*states[-1], cfg, 1e-4, seg, tauo, pro))
+    fL, gL = (x.clone().requires_grad_(True) for x in states[-1])
+    ((O.diagnostics(fL, gL, cfg)["T"] - tgt.cpu()) ** 2).sum().backward()
+    cf, cg = fL.grad, gL.grad
+    for k in reversed(range(nsteps // seg)):
+        fi, gi = (x.clone().requires_grad_(True) for x in states[k])
+        fo, go = O.run(fi, gi, cfg, 1e-4, seg, tauo, pro)
+        torch.autograd.backward([fo, go], [cf, cg])
+        cf, cg = fi.grad, gi.grad
+        del fo, go, fi, gi
+        states[k + 1] = None
+    torch.autograd.backward([f0, g0], [cf, cg])
+    for K, (gT, gtau, gpr) in grads.items():
+        e = (rel(gT, T0o.grad), abs(gtau / float(tauo.grad) - 1), abs(gpr / float(pro.grad) - 1))
+        print(f"[rollout 256^2, {nsteps} steps, K {K}] against the oracle: T0 {e[0]:.1e}, tau_ref {e[1]:.1e}, "
+              f"Pr {e[2]:.1e}", flush=True)
+        assert max(e) < 1e-10, (K, e)
+
+
 @pytest.mark.parametrize("K", (10, 50))
 def test_adjoint_vs_central_differences_256(K):
     """256^2 periodic, 200 steps, loss sum (T - T_target)^2: parameter and
