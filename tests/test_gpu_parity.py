@@ -397,24 +397,28 @@ def test_vortex_1024_300_steps_against_the_oracle():
         assert max(errs.values()) < tol, (storage, errs)
 
 
-def test_shock_vortex_2048x1024_100_steps_against_the_oracle():
-    """The 2048 x 1024 shock-vortex workload (Pr 0.71, gamma 1.4, x
-    zero-gradient, y periodic) over 100 steps against the oracle's own
-    full-size run of the same steps (tests/golden/shock_vortex_2048x1024_oracle_100.npz,
-    written by tests/golden/make_shock_vortex_reference.py from the oracle
-    alone, with the time step it used): rho and T on the 128 x 64 grid of
-    16 x 16 block averages and at 256 sampled cells, the x edges included.
-    Float64 storage within 1e-12 (measured 2.4e-16 to 5.5e-16), FP32 and
-    FP32-dev within 2e-6 (measured 1.3e-7 to 2.4e-7 and 3.3e-7 to 7.6e-7:
-    at Mach 1.2 the deviations from the rest state are as large as the
-    values, so FP32-dev does not gain here)."""
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "shock_vortex_2048x1024_oracle_100.npz")
+@pytest.mark.parametrize("Pr,gamma,name", (
+    (0.71, 1.4, "shock_vortex_2048x1024_oracle_100.npz"),
+    (2.0, 5.0 / 3.0, "shock_vortex_2048x1024_Pr2_gamma5-3_oracle_100.npz")), ids=("Pr0.71-g1.4", "Pr2-g5/3"))
+def test_shock_vortex_2048x1024_100_steps_against_the_oracle(Pr, gamma, name):
+    """The 2048 x 1024 shock-vortex workload (x zero-gradient, y periodic) at
+    two (Pr, gamma) pairs, one for each side of Table I (Pr < 1 and Pr > 1),
+    over 100 steps against the oracle's own full-size run of the same steps
+    (tests/golden/*.npz, written by tests/golden/make_shock_vortex_reference.py
+    from the oracle alone, with the time step it used): rho and T on the
+    128 x 64 grid of 16 x 16 block averages and at 256 sampled cells, the x
+    edges included.  Float64 storage within 1e-12, FP32 and FP32-dev within
+    2e-6 (measured at Pr 0.71, gamma 1.4: 2.4e-16 to 5.5e-16, 1.3e-7 to
+    2.4e-7 and 3.3e-7 to 7.6e-7; at Pr 2, gamma 5/3: 1.7e-16 to 4.7e-16,
+    5.0e-8 to 1.1e-7 and 1.1e-7 to 2.8e-7; at Mach 1.2 the deviations from
+    the rest state are as large as the values, so FP32-dev does not gain)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
     ref = np.load(path)
     ys, xs = torch.tensor(ref["ys"]), torch.tensor(ref["xs"])
-    wl = shock_vortex(2048, 1024, mach_s=1.2, mach_v=0.25, r_frac=0.075, gamma=1.4)
+    wl = shock_vortex(2048, 1024, mach_s=1.2, mach_v=0.25, r_frac=0.075, gamma=gamma)
     pool = torch.nn.functional.avg_pool2d
     for storage, tol in (("f64", 1e-12), ("f32", 2e-6), ("f32_dev", 2e-6)):
-        s, _ = solver(wl, split=2, storage=storage, Pr=0.71, gamma=1.4, tau_ref=wl.phys["mu"], bc_x="zero_gradient",
+        s, _ = solver(wl, split=2, storage=storage, Pr=Pr, gamma=gamma, tau_ref=wl.phys["mu"], bc_x="zero_gradient",
                       bc_y="periodic", dt=float(ref["dt"]))
         s.step(int(ref["steps"]))
         m = s.moments(fields=True, sums=False)
@@ -424,7 +428,7 @@ def test_shock_vortex_2048x1024_100_steps_against_the_oracle():
             f = m[k]
             errs[k + "_blocks"] = rel(pool(f[None, None], 16)[0, 0].cpu(), torch.tensor(ref[k + "_blocks"]))
             errs[k + "_samples"] = rel(f[ys.to(f.device), xs.to(f.device)].cpu(), torch.tensor(ref[k + "_samples"]))
-        print(f"[shock-vortex 2048x1024, 100 steps, oracle] {storage}: "
+        print(f"[shock-vortex 2048x1024, Pr {Pr}, gamma {gamma:.3f}, 100 steps, oracle] {storage}: "
               + ", ".join(f"{k} {v:.1e}" for k, v in errs.items()), flush=True)
         assert max(errs.values()) < tol, (storage, errs)
 
@@ -449,6 +453,29 @@ def test_thermal_wave_4096_sampled(storage, tol):
     s.step(1)
     got, ref, before = sampled_check(s, p, nsamples=64)
     check_sampled(got, ref, before, storage, tol, "thermal wave 4096")
+
+
+@pytest.mark.parametrize("storage,u", (("bf16_dev", 2.0 ** -8), ("fp16_dev", 2.0 ** -11)))
+def test_thermal_wave_4096_sampled_16bit(storage, u):
+    """The 4096^2 thermal wave in the 16-bit deviation formats: one step on
+    64 sampled cells against the oracle's update of the same (decoded) state.
+    The stored value is the format's rounding of the deviation from the rest
+    equilibrium, so the difference is bounded by 1.5 units of the format
+    times the deviation's size (as on the small grids); measured 0.016 units
+    (BF16) and 0.020 (FP16): a step moves most stored deviations by less
+    than their rounding unit."""
+    wl = thermal_wave(4096, seed=0)
+    s, p = solver(wl, split=2, storage=storage, Pr=0.5, tau_ref=5e-5)
+    s.step(1)
+    got, ref, before = sampled_check(s, p, nsamples=64)
+    cfg = oracle_cfg(p)
+    fr, gr = O.initial_state(np.ones((1, 1)), np.zeros((1, 1)), np.zeros((1, 1)), np.full((1, 1), p.T_ref), cfg)
+    xref = torch.stack([fr[:, 0, 0], gr[:, 0, 0]])[:, :, None]  # rest equilibrium per plane, [2, Q, 1]
+    e = float(torch.linalg.vector_norm(got - ref))
+    dev = float(torch.linalg.vector_norm(ref - xref))
+    print(f"[thermal wave 4096] {storage}: |got - oracle| / |deviation| = {e / dev:.2e} = {e / (u * dev):.3f} u",
+          flush=True)
+    assert e <= 1.5 * u * dev
 
 
 def test_largest_grids_sampled():
