@@ -5,7 +5,8 @@ DDF-QE DVBM from the equilibrium of ``(rho0, u0, T0)`` and returns the final
 temperature field; its backward pass is the discrete adjoint of the library
 (``dvbm_adjoint_*``), with checkpoints every ``K`` steps and recomputation of
 each segment's states during the reverse sweep (optionally on a second stream,
-one segment ahead of the sweep). The time step is held fixed
+one segment ahead of the sweep); the last segment's states are kept by the
+forward pass, which steps through them anyway. The time step is held fixed
 (it must be given explicitly), so the gradient is that of the fixed-dt map.
 
 Argument marshalling only: forward and reverse sweeps run in the HIP kernels.
@@ -31,7 +32,21 @@ class _Rollout(torch.autograd.Function):
         while n < nsteps:
             ckpts.append(s.state_buffer.clone())
             k = min(K, nsteps - n)
-            s.step(k)
+            if n + k < nsteps:
+                s.step(k)
+            else:
+                # the last segment steps through a buffer of its k - 1 intermediate states, which the
+                # reverse sweep then reads as they are instead of recomputing them (same kernel, same
+                # results); the final step lands in the solver's other buffer, made current
+                last = torch.empty((max(k - 1, 1), s.buffers[0].numel()), dtype=torch.uint8, device=T0.device)
+                prev = ckpts[-1]
+                for j in range(k - 1):
+                    s.step_from(prev, last[j])
+                    prev = last[j]
+                other = 1 - s.state_index
+                s.step_from(prev, s.buffers[other])
+                s.set_state_index(other)
+                ctx.last = [ckpts[-1]] + [last[j] for j in range(k - 1)]
             n += k
         out = s.moments(fields=True, sums=False)["T"]
         ctx.solver = s
@@ -89,7 +104,9 @@ class _Rollout(torch.autograd.Function):
             ready[seg].record(side)
             return states
 
-        pending = {nseg - 1: recompute(nseg - 1)}
+        # the last segment's states were kept by the forward pass
+        ready[nseg - 1].record(main)
+        pending = {nseg - 1: ctx.last}
         for seg in reversed(range(nseg)):
             states = pending.pop(seg)
             if ctx.overlap and seg > 0:
@@ -123,9 +140,10 @@ def rollout_temperature(T0: torch.Tensor, tau_ref: torch.Tensor, Pr: torch.Tenso
     parameters of :func:`make_params` (``dx``, ``dy``, ``split``, ``storage``,
     boundaries, ``gamma`` ... and an explicit ``dt``).  ``overlap`` recomputes
     the next segment on a second stream during each reverse sweep, at the cost
-    of a second buffer of ``K - 1`` states (on a 256 x 256 grid the two streams
-    slow each other down: the reverse sweep's kernels already keep the memory
-    system busy).  ``cotangent="f32"`` stores the cotangents of the reverse
+    of a second buffer of ``K - 1`` states and a second handle; the gradient is
+    the same bit for bit (on a 256 x 256 grid it saves about a tenth of a
+    forward run: the reverse sweep's kernels leave little room on the SIMDs).
+    ``cotangent="f32"`` stores the cotangents of the reverse
     sweep in float32 (``dvbm_adjoint_step_f32``; the arithmetic stays float64),
     which halves their memory traffic at one float32 rounding per value and step.
     """
