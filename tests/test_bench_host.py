@@ -104,3 +104,15 @@ def test_write_profiles_calibrates_against_the_probes(tmp_path):
         adj = fh.read()
     # 64 KiB x 2 read and 32 KiB written over 256^2 cells: 2 and 0.5 bytes per cell in 0.5 us
     assert "| `k_adjoint_relax<2, StoreF64, 1, double>` | 256 | 1 | 0.5 | 2 | 0 | 328 |" in adj
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N with N > 1 exits (status 2) with a message saying the library runs on one GPU."""
+    import subprocess
+    import sys
+
+    res = subprocess.run([sys.executable, os.path.join(bench.ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode == 2
+    msg = json.loads(res.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
