@@ -37,8 +37,12 @@ class _Rollout(torch.autograd.Function):
             else:
                 # the last segment steps through a buffer of its k - 1 intermediate states, which the
                 # reverse sweep then reads as they are instead of recomputing them (same kernel, same
-                # results); the final step lands in the solver's other buffer, made current
-                last = torch.empty((max(k - 1, 1), s.buffers[0].numel()), dtype=torch.uint8, device=T0.device)
+                # results), and afterwards reuses for recomputing the segments before it (so it holds
+                # K - 1 states when there are such segments); the final step lands in the solver's
+                # other buffer, made current
+                rows = max((K if n > 0 else k) - 1, 1)
+                last = torch.empty((rows, s.buffers[0].numel()), dtype=torch.uint8, device=T0.device)
+                ctx.last_buf = last
                 prev = ckpts[-1]
                 for j in range(k - 1):
                     s.step_from(prev, last[j])
@@ -74,17 +78,21 @@ class _Rollout(torch.autograd.Function):
         # turns.  Without, one buffer and one stream, recomputing after each sweep.
         main = s.stream
         nb = s.buffers[0].numel()
+        # the forward pass's last-segment buffer is one of them: segment nseg - 1 is read from it,
+        # and the segments of the same parity are recomputed into it afterwards
         if ctx.overlap:
             side = torch.cuda.Stream(device=dev)
             side.wait_stream(main)  # the checkpoints and the forward state are ready
             r = Solver(s.params, *ctx.fields0, device=dev, stream=side)
-            bufs = [torch.empty((max(K - 1, 1), nb), dtype=torch.uint8, device=dev) for _ in range(2)]
+            bufs = [None, None]
+            bufs[(nseg - 1) % 2] = ctx.last_buf
+            bufs[nseg % 2] = torch.empty((max(K - 1, 1), nb), dtype=torch.uint8, device=dev) if nseg > 1 else None
             # memory the side stream uses is not handed out again before its work is done
-            for tns in bufs + ctx.ckpts + r.buffers + [r.workspace] + list(r._fields0):
+            for tns in [b for b in bufs if b is not None] + ctx.ckpts + r.buffers + [r.workspace] + list(r._fields0):
                 tns.record_stream(side)
         else:
             side, r = main, s
-            bufs = [torch.empty((max(K - 1, 1), nb), dtype=torch.uint8, device=dev)] * 2
+            bufs = [ctx.last_buf] * 2
         ready = [torch.cuda.Event() for _ in range(nseg)]
         free = [None, None]  # event on main after the last reverse sweep that read bufs[k]
 
