@@ -157,5 +157,7 @@ def rollout_temperature(T0: torch.Tensor, tau_ref: torch.Tensor, Pr: torch.Tenso
     """
     if cotangent not in ("f64", "f32"):
         raise ValueError("cotangent must be 'f64' or 'f32'")
+    if int(nsteps) < 1 or int(K) < 1:
+        raise ValueError("rollout_temperature needs nsteps >= 1 and a checkpoint interval K >= 1")
     return _Rollout.apply(T0, tau_ref, Pr, rho0, ux0, uy0, int(nsteps), int(K), bool(overlap), cotangent,
                           dict(params_kw))

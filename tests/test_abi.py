@@ -157,3 +157,17 @@ def test_new_entry_points_reject_null_handles():
     p = ctypes.c_void_p(4096)
     assert lib.dvbm_limiter_signature(None, p, p) == dvbm.DVBM_EINVAL
     assert lib.dvbm_adjoint_step_noalloc(None, p, p, p, None) == dvbm.DVBM_EINVAL
+
+
+def test_rollout_rejects_bad_step_counts():
+    """rollout_temperature refuses nsteps < 1 and a checkpoint interval K < 1
+    (K = 0 would never advance) before it touches a device."""
+    import torch
+
+    from paper_2510_04197_amd import rollout_temperature
+
+    T0 = torch.ones((4, 4), dtype=torch.float64)
+    one = torch.tensor(1.0, dtype=torch.float64)
+    for nsteps, K in ((0, 10), (10, 0), (5, -1)):
+        with pytest.raises(ValueError, match="nsteps >= 1 and a checkpoint interval K >= 1"):
+            rollout_temperature(T0, one, one, None, None, None, nsteps, K=K, dt=1e-3)
