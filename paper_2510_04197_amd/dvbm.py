@@ -138,6 +138,11 @@ def stream_probe(src: torch.Tensor | None, dst: torch.Tensor, nbytes: int, mode:
     """``dvbm_stream_probe``: plain streaming copy (mode 0), read (1) or write (2) of ``nbytes``;
     mode + 4 makes the accesses non-temporal."""
     lib = load_library()
+    dev = torch.device("cuda")
+    kind = int(mode) & 3
+    _need(dst, "dst", dev, nbytes=int(width) if kind == 1 else int(nbytes))
+    if kind != 2 or src is not None:
+        _need(src, "src", dev, nbytes=int(nbytes))
     _check(lib.dvbm_stream_probe(_ptr(src) if src is not None else None, _ptr(dst), int(nbytes), int(mode),
                                  int(width), ctypes.c_void_p(stream.cuda_stream)))
 
@@ -159,6 +164,26 @@ def _dev_f64(a, device):
 
 def _ptr(t: torch.Tensor):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, what: str, device: torch.device, nbytes: int | None = None, dtype: torch.dtype | None = None,
+          shape=None) -> torch.Tensor:
+    """A tensor handed to the library as a plain pointer: on ``device``, contiguous, of ``dtype`` and
+    ``shape`` when given, and of at least ``nbytes`` bytes when given (the library trusts the sizes it
+    is given, so a short buffer would be read or written out of bounds)."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    if t.device.type != device.type or (device.index is not None and t.device.index != device.index):
+        raise ValueError(f"{what} must be on {device}, not {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, not {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} must have shape {tuple(shape)}, not {tuple(t.shape)}")
+    if nbytes is not None and t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{what} holds {t.numel() * t.element_size()} bytes, fewer than the {nbytes} it needs")
+    return t
 
 
 class Solver:
@@ -196,8 +221,14 @@ class Solver:
     def step(self, nsteps: int = 1):
         _check(self.lib.dvbm_step(self._h(), int(nsteps)))
 
+    def _pop_shape(self):
+        return (2, self.Q, self.params.ny, self.params.nx)
+
     def step_from(self, src: torch.Tensor, dst: torch.Tensor):
         """One step from the population buffer ``src`` into ``dst``; the solver's own state is unchanged."""
+        nb = self.buffers[0].numel()
+        _need(src, "src", self.device, nbytes=nb)
+        _need(dst, "dst", self.device, nbytes=nb)
         _check(self.lib.dvbm_step_from(self._h(), _ptr(src), _ptr(dst)))
 
     @property
@@ -256,6 +287,7 @@ class Solver:
         float32 (``dvbm_adjoint_step_f32``: float32 storage, float64 arithmetic)."""
         if lam_next.dtype != lam.dtype or lam.dtype not in (torch.float64, torch.float32):
             raise TypeError("lam_next and lam must both be float64 or both float32")
+        self._check_adjoint_args(state, lam_next, lam, dparams, lam.dtype)
         if getattr(self, "_adj_work", None) is None:
             nbytes = self.lib.dvbm_adjoint_work_bytes(ctypes.byref(self.params))
             self._adj_work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -269,13 +301,25 @@ class Solver:
         array; the library's fixed per-device scratch holds it (grids up to 149,211 cells)."""
         if lam_next.dtype != torch.float64 or lam.dtype != torch.float64:
             raise TypeError("lam_next and lam must be float64")
+        self._check_adjoint_args(state, lam_next, lam, dparams, torch.float64)
         _check(self.lib.dvbm_adjoint_step_noalloc(self._h(), _ptr(state), _ptr(lam_next), _ptr(lam),
                                                   _ptr(dparams) if dparams is not None else None))
 
+    def _check_adjoint_args(self, state, lam_next, lam, dparams, dtype):
+        _need(state, "state", self.device, nbytes=self.buffers[0].numel())
+        _need(lam_next, "lam_next", self.device, dtype=dtype, shape=self._pop_shape())
+        _need(lam, "lam", self.device, dtype=dtype, shape=self._pop_shape())
+        if dparams is not None:
+            _need(dparams, "dparams", self.device, dtype=torch.float64, nbytes=16)
+
     def adjoint_moments(self, state: torch.Tensor, d_rho=None, d_ux=None, d_uy=None, d_T=None) -> torch.Tensor:
         """Cotangent of the populations of ``state`` from cotangents of its fields."""
+        _need(state, "state", self.device, nbytes=self.buffers[0].numel())
         lam = self.new_cotangent()
         cot = [None if a is None else _dev_f64(a, self.device) for a in (d_rho, d_ux, d_uy, d_T)]
+        for a, name in zip(cot, ("d_rho", "d_ux", "d_uy", "d_T")):
+            if a is not None:
+                _need(a, name, self.device, shape=(self.params.ny, self.params.nx))
         _check(self.lib.dvbm_adjoint_moments(self._h(), _ptr(state), *[_ptr(a) if a is not None else None
                                                                           for a in cot], _ptr(lam)))
         self._keep = cot
@@ -283,8 +327,11 @@ class Solver:
 
     def adjoint_init(self, lam0: torch.Tensor, rho, ux, uy, T, which=("T",)):
         """Cotangents of the initial fields named in ``which`` (subset of rho, ux, uy, T)."""
+        _need(lam0, "lam0", self.device, dtype=torch.float64, shape=self._pop_shape())
         fields = [_dev_f64(a, self.device) for a in (rho, ux, uy, T)]
         names = ("rho", "ux", "uy", "T")
+        for a, name in zip(fields, names):
+            _need(a, name, self.device, shape=(self.params.ny, self.params.nx))
         outs = {k: torch.zeros_like(fields[0]) for k in which}
         _check(self.lib.dvbm_adjoint_init(self._h(), _ptr(lam0), *[_ptr(f) for f in fields],
                                           *[_ptr(outs[k]) if k in outs else None for k in names]))
@@ -296,6 +343,8 @@ class Solver:
         device ``int64`` scalar tensor ``out`` (``dvbm_limiter_signature``; a sum modulo 2^64)."""
         if out.dtype != torch.int64 or out.numel() != 1 or out.device.type != self.device.type:
             raise TypeError("out must be a one-element int64 device tensor")
+        _need(state, "state", self.device, nbytes=self.buffers[0].numel())
+        _need(out, "out", self.device)
         _check(self.lib.dvbm_limiter_signature(self._h(), _ptr(state), _ptr(out)))
 
     def close(self):

@@ -171,3 +171,26 @@ def test_rollout_rejects_bad_step_counts():
     for nsteps, K in ((0, 10), (10, 0), (5, -1)):
         with pytest.raises(ValueError, match="nsteps >= 1 and a checkpoint interval K >= 1"):
             rollout_temperature(T0, one, one, None, None, None, nsteps, K=K, dt=1e-3)
+
+
+def test_binding_checks_every_tensor_before_the_call():
+    """Pointers reach the library without sizes of their own, so the binding refuses a tensor on another
+    device, a strided view, a wrong dtype or shape, and a buffer shorter than the call needs."""
+    import torch
+
+    from paper_2510_04197_amd import dvbm
+    cpu = torch.device("cpu")
+    t = torch.zeros((2, 5, 3, 4), dtype=torch.float64)
+    assert dvbm._need(t, "t", cpu, nbytes=t.numel() * 8, dtype=torch.float64, shape=(2, 5, 3, 4)) is t
+    with pytest.raises(TypeError):
+        dvbm._need(np.zeros(4), "t", cpu)
+    with pytest.raises(ValueError, match="must be on"):
+        dvbm._need(t, "t", torch.device("cuda"))
+    with pytest.raises(ValueError, match="contiguous"):
+        dvbm._need(t.transpose(2, 3), "t", cpu)
+    with pytest.raises(TypeError, match="float32"):
+        dvbm._need(t, "t", cpu, dtype=torch.float32)
+    with pytest.raises(ValueError, match="shape"):
+        dvbm._need(t, "t", cpu, shape=(2, 5, 4, 3))
+    with pytest.raises(ValueError, match="fewer"):
+        dvbm._need(t, "t", cpu, nbytes=t.numel() * 8 + 1)

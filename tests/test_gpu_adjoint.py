@@ -566,3 +566,38 @@ def test_fp32_adjoint_close_to_fp64():
     for st in ("f32", "f32_dev"):
         print("%s storage: gradient relative L2 against float64 storage %.2e" % (st, rel(grads[st], grads["f64"])))
         assert rel(grads[st], grads["f64"]) < 5e-3
+
+
+@pytest.mark.parametrize("storage", ("f64", "f32_dev"))
+def test_binding_refuses_short_or_strided_tensors(storage):
+    """The binding checks every tensor before the library sees its pointer: a short population buffer,
+    a cotangent of the wrong shape, dtype or layout, and a host tensor are refused, and the refused
+    calls leave the state and the good cotangent untouched."""
+    print(f"[binding checks] {storage}", flush=True)
+    wl = smooth_random(20, 12, seed=3)
+    p = make_params(wl.nx, wl.ny, dx=wl.dx, dy=wl.dy, split=2, storage=storage, tau_ref=0.02, dt=3e-3)
+    s = Solver(p, wl.rho, wl.ux, wl.uy, wl.T, device=DEV)
+    state = s.state_buffer
+    before = state.clone()
+    good = s.new_cotangent()
+    lam1 = torch.ones_like(good)
+    with pytest.raises(ValueError, match="fewer"):
+        s.step_from(state, torch.empty(state.numel() - 1, dtype=torch.uint8, device=DEV))
+    with pytest.raises(ValueError, match="fewer"):
+        s.adjoint_step(state[:-8], lam1, good)
+    with pytest.raises(ValueError, match="shape"):
+        s.adjoint_step(state, lam1[:, :, :-1].contiguous(), good[:, :, :-1].contiguous())
+    with pytest.raises(ValueError, match="contiguous"):
+        s.adjoint_step(state, lam1, good.transpose(2, 3))
+    with pytest.raises(TypeError):
+        s.adjoint_step(state, lam1, good, torch.zeros(2, dtype=torch.float32, device=DEV))
+    with pytest.raises(ValueError, match="must be on"):
+        s.adjoint_step(state, lam1.cpu(), good.cpu())
+    with pytest.raises(ValueError, match="shape"):
+        s.adjoint_moments(state, d_T=torch.ones(p.ny, p.nx + 1, dtype=torch.float64, device=DEV))
+    torch.cuda.synchronize()
+    assert torch.equal(state, before)
+    assert not torch.any(good)
+    s.adjoint_step(state, lam1, good)
+    torch.cuda.synchronize()
+    assert torch.isfinite(good).all() and torch.any(good)
