@@ -26,9 +26,12 @@
  *  - Macroscopic fields are dense row-major float64 arrays of ny*nx values,
  *    element (y, x) at index y*nx + x; cell (y, x) has its centre at
  *    ((x + 1/2) dx, (y + 1/2) dy).
- *  - Population buffers use the structure-of-arrays layout
- *        element (d, i, y, x) at index ((d*Q + i)*ny + y)*pitch + x,
- *    d = 0 for f and d = 1 for g, pitch = dvbm_pitch(p) elements.
+ *  - Population buffers hold each distribution row by row, the Q planes of a
+ *    row side by side:
+ *        element (d, i, y, x) at index ((d*ny + y)*Q + i)*pitch + x,
+ *    d = 0 for f and d = 1 for g, pitch = dvbm_pitch(p) elements.  The dense
+ *    float64 arrays of dvbm_load_populations, dvbm_store_populations and the
+ *    adjoint cotangents are [2][Q][ny][nx] instead.
  *    Population i = a*q1 + b has velocity sqrt(R T_ref) (xi_a, xi_b) and
  *    weight w_a w_b, with the 1-D Gauss-Hermite nodes xi ascending
  *    (q1 = 4 for split I, Q = 16; q1 = 5 for split II, Q = 25).

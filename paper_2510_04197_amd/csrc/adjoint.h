@@ -349,7 +349,7 @@ template <int SPLIT, class S>
 __device__ inline double adj_X(const typename S::T* __restrict__ state, const KParams& kp, int d, int i, int y,
                                int x) {
   constexpr int Q = Set<SPLIT>::Q;
-  const typename S::T v = state[int64_t(d * Q + i) * kp.plane + int64_t(y) * kp.pitch + x];
+  const typename S::T v = state[sidx(kp, d, i, y, x)];
   if (!S::dev) return double(S::raw(v));
   const double r = d == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i);
   return weight<SPLIT>(i) * (r + double(S::raw(v)));

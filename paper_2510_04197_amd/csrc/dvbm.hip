@@ -227,12 +227,11 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho, co
     for (int i = 0; i < Q; ++i) f[i] = g[i] = 0.0;
     expand_add<N1, NF>(bf, f);
     expand_add<N1, 2>(bg, g);
-    const int64_t off = int64_t(y) * kp.pitch + x;
     for (int i = 0; i < Q; ++i) {
       const double w = weight<SPLIT>(i);
       using C = typename S::C;
-      dst[int64_t(i) * kp.plane + off] = S::enc64(f[i], w, 1.0);
-      dst[int64_t(Q + i) * kp.plane + off] = S::enc64(g[i], w, g_ref_over_w<SPLIT>(kp, i));
+      dst[sidx(kp, 0, i, y, x)] = S::enc64(f[i], w, 1.0);
+      dst[sidx(kp, 1, i, y, x)] = S::enc64(g[i], w, g_ref_over_w<SPLIT>(kp, i));
     }
   }
 }
@@ -265,11 +264,10 @@ __global__ __launch_bounds__(256) void k_wall_ghosts(const typename S::T* __rest
   const int r = t / kp.nx, x = t - r * kp.nx;
   const int yb = r == 0 ? 1 : (r == 1 ? 0 : (r == 2 ? kp.ny - 1 : kp.ny - 2));
   const int wall = r < 2 ? 0 : 1;
-  const int64_t off = int64_t(yb) * kp.pitch + x;
   double f[Q], g[Q];
   for (int i = 0; i < Q; ++i) {
-    f[i] = decode_one<SPLIT, S>(src[int64_t(i) * kp.plane + off], 0, i, kp);
-    g[i] = decode_one<SPLIT, S>(src[int64_t(Q + i) * kp.plane + off], 1, i, kp);
+    f[i] = decode_one<SPLIT, S>(src[sidx(kp, 0, i, yb, x)], 0, i, kp);
+    g[i] = decode_one<SPLIT, S>(src[sidx(kp, 1, i, yb, x)], 1, i, kp);
   }
   // the boundary cell's rho, u, T (Eqs. eq_quadratur1-3 and eq:Total_energy_MB)
   const NodeMoments m = node_moments<N1>(f, g);
@@ -297,7 +295,7 @@ __global__ __launch_bounds__(256) void k_decode(const typename S::T* __restrict_
     const int di = int(k / cells);
     const int64_t c = k % cells;
     const int y = int(c / kp.nx), x = int(c % kp.nx);
-    X[k] = decode_one<SPLIT, S>(src[int64_t(di) * kp.plane + int64_t(y) * kp.pitch + x], di / Q, di % Q, kp);
+    X[k] = decode_one<SPLIT, S>(src[sidx(kp, di / Q, di % Q, y, x)], di / Q, di % Q, kp);
   }
 }
 
@@ -313,7 +311,7 @@ __global__ __launch_bounds__(256) void k_encode(const double* __restrict__ X, ty
     const int y = int(c / kp.nx), x = int(c % kp.nx);
     const double w = weight<SPLIT>(i);
     const double r = d == 0 ? 1.0 : g_ref_over_w<SPLIT>(kp, i);
-    dst[int64_t(di) * kp.plane + int64_t(y) * kp.pitch + x] = S::enc64(X[k], w, r);
+    dst[sidx(kp, d, i, y, x)] = S::enc64(X[k], w, r);
   }
 }
 
@@ -348,11 +346,10 @@ __global__ __launch_bounds__(RED_THREADS) void k_moments(const typename S::T* __
   const double c = sqrt(kp.c2);
   for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x) {
     const int y = int(k / kp.nx), x = int(k % kp.nx);
-    const int64_t off = int64_t(y) * kp.pitch + x;
     double f[Q], g[Q];
     for (int i = 0; i < Q; ++i) {
-      f[i] = decode_one<SPLIT, S>(src[int64_t(i) * kp.plane + off], 0, i, kp);
-      g[i] = decode_one<SPLIT, S>(src[int64_t(Q + i) * kp.plane + off], 1, i, kp);
+      f[i] = decode_one<SPLIT, S>(src[sidx(kp, 0, i, y, x)], 0, i, kp);
+      g[i] = decode_one<SPLIT, S>(src[sidx(kp, 1, i, y, x)], 1, i, kp);
     }
     const NodeMoments m = node_moments<N1>(f, g);
     const double rho = m.rho, jx = c * m.jx, jy = c * m.jy;
@@ -488,11 +485,10 @@ __global__ __launch_bounds__(256) void k_adjoint_readout(const typename S::T* __
   const int64_t n = int64_t(kp.nx) * kp.ny;
   for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x) {
     const int y = int(k / kp.nx), x = int(k % kp.nx);
-    const int64_t off = int64_t(y) * kp.pitch + x;
     double f[Q], g[Q], lf[Q], lg[Q];
     for (int i = 0; i < Q; ++i) {
-      f[i] = decode_one<SPLIT, S>(state[int64_t(i) * kp.plane + off], 0, i, kp);
-      g[i] = decode_one<SPLIT, S>(state[int64_t(Q + i) * kp.plane + off], 1, i, kp);
+      f[i] = decode_one<SPLIT, S>(state[sidx(kp, 0, i, y, x)], 0, i, kp);
+      g[i] = decode_one<SPLIT, S>(state[sidx(kp, 1, i, y, x)], 1, i, kp);
     }
     const NodeMoments m = node_moments<N1>(f, g);
     readout_adjoint_cell<SPLIT>(m, kp, rb ? rb[k] : 0.0, uxb ? uxb[k] : 0.0, uyb ? uyb[k] : 0.0, Tb ? Tb[k] : 0.0,
@@ -548,7 +544,7 @@ __device__ inline int limiter_branch(double a, double b, double beta) {
 }
 
 // Signature of the limiter branches of one step from float64 populations X
-// (dense planes with row pitch kp.pitch): for every population plane with a
+// (a population buffer in float64 storage): for every population plane with a
 // non-zero velocity component along an axis, the face above each cell along
 // that axis is reconstructed from its upwind side (v > 0: cells c-1, c, c+1;
 // v < 0: c, c+1, c+2), and sig receives the sum, over those faces, of
@@ -567,14 +563,13 @@ __global__ __launch_bounds__(256) void k_limiter_signature(const double* __restr
   for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x) {
     const int y = int(k / kp.nx), x = int(k % kp.nx);
     for (int pl = 0; pl < 2 * Q; ++pl) {
-      const double* P = X + int64_t(pl) * kp.plane;
       const int i = pl % Q;
       for (int ax = 0; ax < 2; ++ax) {
         const double v = ax == 0 ? L::xi(i / N1) : L::xi(i % N1);
         if (v == 0.0) continue;
         auto at = [&](int d) -> double {
-          if (ax == 0) return P[int64_t(y) * kp.pitch + wrap_any<BCX>(x + d, kp.nx)];
-          return P[int64_t(wrap_any<BCY>(y + d, kp.ny)) * kp.pitch + x];
+          if (ax == 0) return X[sidx(kp, pl / Q, i, y, wrap_any<BCX>(x + d, kp.nx))];
+          return X[sidx(kp, pl / Q, i, wrap_any<BCY>(y + d, kp.ny), x)];
         };
         const double a = v > 0.0 ? at(0) - at(-1) : at(1) - at(2);
         const double b = v > 0.0 ? at(1) - at(0) : at(0) - at(1);
@@ -717,7 +712,8 @@ KParams make_kparams(const dvbm_params& p, double dt) {
   k.nx = p.nx;
   k.ny = p.ny;
   k.pitch = dvbm_pitch(&p);
-  k.plane = k.pitch * p.ny;
+  k.srow = k.pitch * (p.split == 1 ? 16 : 25);
+  k.sdist = k.srow * p.ny;
   k.c2 = p.R * p.T_ref;
   k.R = p.R;
   k.Cv = p.R / (p.gamma - 1.0);
@@ -792,7 +788,7 @@ inline int step_kernel(const dvbm_handle* h) {
   if (h->p.kernel != DVBM_KERNEL_AUTO) return h->p.kernel;
   const bool big = int64_t(h->p.nx) * h->p.ny >= SWEEP_MIN_CELLS;
   if (h->p.storage == DVBM_F64) return DVBM_SWEEP && big ? DVBM_KERNEL_SWEEP : DVBM_KERNEL_TILE;
-  const uint64_t dist = uint64_t(h->kp.plane) * h->Q * uint64_t(storage_bytes(h->p.storage));
+  const uint64_t dist = uint64_t(h->kp.sdist) * uint64_t(storage_bytes(h->p.storage));
   if (DVBM_SWEEP && big && dist <= (uint64_t(1) << 31))
     return DVBM_KERNEL_SWEEP;
   return DVBM_KERNEL_CELL;

@@ -30,7 +30,9 @@ struct Set {
 // Kernel constants (all physical input scaled once on the host).
 struct KParams {
   int nx, ny;
-  int64_t pitch, plane;  // elements per row / per population plane
+  int64_t pitch;         // elements per row of one population plane (nx rounded up to 64)
+  int64_t srow, sdist;   // population buffers: elements per row of one distribution (Q pitch)
+                         // and per distribution (ny srow)
   double c2;             // R T_ref: square of the lattice velocity scale
   double R, Cv, inv_Cv;
   double kx, ky;         // dt sqrt(R T_ref) / dx, dt sqrt(R T_ref) / dy
@@ -42,6 +44,14 @@ struct KParams {
   double wall_T[2];      // no-slip walls in y (below row 0, above row ny-1): temperature
   double wall_ux[2];     // and x velocity of each wall (physical units)
 };
+
+// Element index of population i of distribution d (0: f, 1: g) at cell (x, y)
+// in a population buffer.  Buffers are [2][ny][Q][pitch]: a row of one
+// distribution holds its Q planes side by side, so the rows a workgroup
+// advances together are one contiguous span per distribution.
+__host__ __device__ inline int64_t sidx(const KParams& kp, int d, int i, int y, int x) {
+  return int64_t(d) * kp.sdist + int64_t(y) * kp.srow + int64_t(i) * kp.pitch + x;
+}
 
 // ------------------------------------------------------------ storage formats
 // enc: a value computed in the format's arithmetic C -> stored value (the

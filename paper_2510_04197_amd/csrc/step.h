@@ -68,12 +68,21 @@ __device__ inline rsrc_t dist_rsrc(const void* base, int d, uint32_t dist_bytes)
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(p), 0, dist_bytes, RSRC_WORD3);
 }
 
-// One population plane (index pl of 2Q) as its own buffer resource: the
-// stencil-only lanes of the column sweep store to offset 2^31, beyond any
-// plane, and the row offset plus 2^31 stays below 2^32.
+// One dense plane (index pl) of a cotangent array as its own buffer
+// resource: the stencil-only lanes of the adjoint sweep store to offset 2^31,
+// beyond any plane, and the row offset plus 2^31 stays below 2^32.
 __device__ inline rsrc_t plane_rsrc(const void* base, int pl, uint32_t plane_bytes) {
   const char* p = static_cast<const char*>(base) + size_t(pl) * size_t(plane_bytes);
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(p), 0, plane_bytes, RSRC_WORD3);
+}
+
+// Row y of distribution d of a population buffer (its Q planes side by side)
+// as its own buffer resource: the stencil-only lanes of the column sweep
+// store to offset 2^31, beyond any row, also where a distribution exceeds
+// 2^31 bytes (float64 storage).
+__device__ inline rsrc_t row_rsrc(const void* base, int d, uint32_t dist_bytes, int y, uint32_t row_bytes) {
+  const char* p = static_cast<const char*>(base) + size_t(d) * size_t(dist_bytes) + size_t(y) * size_t(row_bytes);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(p), 0, row_bytes, RSRC_WORD3);
 }
 
 template <class T>
@@ -137,19 +146,19 @@ __device__ inline void cell_update(const typename S::T* __restrict__ src, typena
   constexpr uint32_t SZ = sizeof(T);
   using L = GH<N1>;
 
-  const uint32_t pitch = uint32_t(kp.pitch);
-  const uint32_t row0 = uint32_t(y) * pitch;
+  const uint32_t srow = uint32_t(kp.srow);  // a buffer row: the Q planes of one distribution
+  const uint32_t row0 = uint32_t(y) * srow;
   const uint32_t o0 = (row0 + uint32_t(x)) * SZ;
   const uint32_t oxm2 = (row0 + uint32_t(wrap<BCX>(x - 2, kp.nx))) * SZ;
   const uint32_t oxm1 = (row0 + uint32_t(wrap<BCX>(x - 1, kp.nx))) * SZ;
   const uint32_t oxp1 = (row0 + uint32_t(wrap<BCX>(x + 1, kp.nx))) * SZ;
   const uint32_t oxp2 = (row0 + uint32_t(wrap<BCX>(x + 2, kp.nx))) * SZ;
-  const uint32_t oym2 = (uint32_t(wrap<BCY>(y - 2, kp.ny)) * pitch + uint32_t(x)) * SZ;
-  const uint32_t oym1 = (uint32_t(wrap<BCY>(y - 1, kp.ny)) * pitch + uint32_t(x)) * SZ;
-  const uint32_t oyp1 = (uint32_t(wrap<BCY>(y + 1, kp.ny)) * pitch + uint32_t(x)) * SZ;
-  const uint32_t oyp2 = (uint32_t(wrap<BCY>(y + 2, kp.ny)) * pitch + uint32_t(x)) * SZ;
-  const uint32_t plane_bytes = uint32_t(kp.plane) * SZ;
-  const uint32_t dist_bytes = plane_bytes * uint32_t(Q);
+  const uint32_t oym2 = (uint32_t(wrap<BCY>(y - 2, kp.ny)) * srow + uint32_t(x)) * SZ;
+  const uint32_t oym1 = (uint32_t(wrap<BCY>(y - 1, kp.ny)) * srow + uint32_t(x)) * SZ;
+  const uint32_t oyp1 = (uint32_t(wrap<BCY>(y + 1, kp.ny)) * srow + uint32_t(x)) * SZ;
+  const uint32_t oyp2 = (uint32_t(wrap<BCY>(y + 2, kp.ny)) * srow + uint32_t(x)) * SZ;
+  const uint32_t plane_bytes = uint32_t(kp.pitch) * SZ;  // plane i + 1 follows plane i in a row
+  const uint32_t dist_bytes = uint32_t(kp.sdist) * SZ;
   const rsrc_t rsrc_src[2] = {dist_rsrc(src, 0, dist_bytes), dist_rsrc(src, 1, dist_bytes)};
   const rsrc_t rsrc_dst[2] = {dist_rsrc(dst, 0, dist_bytes), dist_rsrc(dst, 1, dist_bytes)};
 
@@ -293,9 +302,9 @@ __device__ inline void tile_update(const typename S::T* __restrict__ src, typena
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
   const int x = bx * TX + tx, y = by * TY + ty;
   const bool valid = x < kp.nx && y < kp.ny;
-  const uint32_t pitch = uint32_t(kp.pitch);
+  const uint32_t srow = uint32_t(kp.srow);  // a buffer row: the Q planes of one distribution
   const uint32_t o0 =
-      (uint32_t(wrap_any<BCY>(y, kp.ny)) * pitch + uint32_t(wrap_any<BCX>(x, kp.nx))) * SZ;
+      (uint32_t(wrap_any<BCY>(y, kp.ny)) * srow + uint32_t(wrap_any<BCX>(x, kp.nx))) * SZ;
   uint32_t hoff[H];
   int hidx[H];
   bool hval[H];
@@ -307,11 +316,11 @@ __device__ inline void tile_update(const typename S::T* __restrict__ src, typena
     if (hval[j]) halo_slot<TX, TY>(s, hy, hx);
     const int gx = wrap_any<BCX>(bx * TX + hx - 2, kp.nx);
     const int gy = wrap_any<BCY>(by * TY + hy - 2, kp.ny);
-    hoff[j] = (uint32_t(gy) * pitch + uint32_t(gx)) * SZ;
+    hoff[j] = (uint32_t(gy) * srow + uint32_t(gx)) * SZ;
     hidx[j] = hy * (TX + 4) + hx;
   }
-  const uint32_t plane_bytes = uint32_t(kp.plane) * SZ;
-  const uint32_t dist_bytes = plane_bytes * uint32_t(Q);
+  const uint32_t plane_bytes = uint32_t(kp.pitch) * SZ;  // plane i + 1 follows plane i in a row
+  const uint32_t dist_bytes = uint32_t(kp.sdist) * SZ;
   const rsrc_t rsrc_src[2] = {dist_rsrc(src, 0, dist_bytes), dist_rsrc(src, 1, dist_bytes)};
   const rsrc_t rsrc_dst[2] = {dist_rsrc(dst, 0, dist_bytes), dist_rsrc(dst, 1, dist_bytes)};
 

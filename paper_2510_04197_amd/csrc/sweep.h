@@ -126,12 +126,12 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
   // stores of the stencil-only lanes go to offset 2^31, which the bounds
   // check of the buffer resource discards: every lane stores, so no branch
   // splits the memory counters.  The resource is the distribution (at most
-  // 2^31 bytes) for 32/16-bit storage and the plane for float64 storage,
+  // 2^31 bytes) for 32/16-bit storage and the row for float64 storage,
   // whose distributions can exceed 2^31 bytes
   const uint32_t vo_st = own ? vo : 0x80000000u;
-  const uint32_t row_bytes = uint32_t(kp.pitch) * SZ;
-  const uint32_t plane_bytes = uint32_t(kp.plane) * SZ;
-  const uint32_t dist_bytes = plane_bytes * uint32_t(Q);
+  const uint32_t row_bytes = uint32_t(kp.srow) * SZ;     // a buffer row: the Q planes side by side
+  const uint32_t plane_bytes = uint32_t(kp.pitch) * SZ;  // plane i + 1 follows plane i in a row
+  const uint32_t dist_bytes = uint32_t(kp.sdist) * SZ;
   const rsrc_t rsrc_src = dist_rsrc(src, D, dist_bytes);
   const rsrc_t rsrc_dst = dist_rsrc(dst, D, dist_bytes);
   const int ny = kp.ny;
@@ -309,7 +309,8 @@ __device__ inline void sweep_update(const typename S::T* __restrict__ src, typen
         if constexpr (S::dev)
           Buf<T>::st(rsrc_dst, uint32_t(i) * plane_bytes + r_st, vo_st, S::enc_dev(xn));
         else if constexpr (sizeof(T) == 8)
-          Buf<T>::st(plane_rsrc(dst, D * Q + i, plane_bytes), r_st, vo_st, S::enc(xn, R(1), R(0)));
+          Buf<T>::st(row_rsrc(dst, D, dist_bytes, y, row_bytes), uint32_t(i) * plane_bytes, vo_st,
+                     S::enc(xn, R(1), R(0)));
         else
           Buf<T>::st(rsrc_dst, uint32_t(i) * plane_bytes + r_st, vo_st, S::enc(xn, R(1), R(0)));
         // the window drops its first row; that register receives the row after the ring's last

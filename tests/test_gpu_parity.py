@@ -681,8 +681,9 @@ def test_rest_state_stores_zero_deviations(split, storage, kernel):
     dt = {"f32_dev": torch.float32, "bf16_dev": torch.bfloat16, "fp16_dev": torch.float16}[storage]
     pitch = dvbm.load_library().dvbm_pitch(ctypes.byref(p))
 
-    def devs():
-        return s.state_buffer.view(dt).reshape(2 * s.Q, p.ny, pitch)[:, :, : p.nx].float()
+    def devs():  # buffer rows hold the Q planes of a distribution side by side
+        b = s.state_buffer.view(dt).reshape(2, p.ny, s.Q, pitch).transpose(1, 2)
+        return b.reshape(2 * s.Q, p.ny, pitch)[:, :, : p.nx].float()
 
     d0 = devs()
     assert float(d0[: s.Q].abs().max()) == 0.0  # f: X / w = 1 exactly
@@ -714,8 +715,8 @@ def test_step_from_matches_step(storage):
     dt = {"f64": torch.float64, "f32": torch.float32, "bf16_dev": torch.int16, "f32_dev": torch.float32}[storage]
     pitch = dvbm.load_library().dvbm_pitch(ctypes.byref(p))
 
-    def cells(buf):
-        return buf.view(dt).reshape(2 * s.Q, p.ny, pitch)[:, :, : p.nx]
+    def cells(buf):  # buffer rows hold the Q planes of a distribution side by side
+        return buf.view(dt).reshape(2, p.ny, s.Q, pitch)[..., : p.nx]
 
     assert torch.equal(cells(s.state_buffer), cells(dst))
 
