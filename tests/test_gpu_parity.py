@@ -699,6 +699,24 @@ def test_rest_state_stores_zero_deviations(split, storage, kernel):
     s.close()
 
 
+@pytest.mark.parametrize("split", (1, 2))
+def test_population_buffer_layout(split):
+    """The population buffer holds element (d, i, y, x) at ((d ny + y) Q + i) pitch + x, as the header
+    states: float64 populations loaded from the dense [2][Q][ny][nx] array are found there bit for bit."""
+    wl = smooth_random(70, 9, seed=4)
+    s, p = solver(wl, split=split, storage="f64", tau_ref=0.02, cfl=0.1)
+    Q = s.Q
+    X = torch.tensor(np.random.default_rng(7).standard_normal((2, Q, p.ny, p.nx)))
+    s.load_populations(X)
+    pitch = dvbm.load_library().dvbm_pitch(ctypes.byref(p))
+    raw = s.state_buffer.view(torch.float64).cpu()
+    assert raw.numel() == 2 * p.ny * Q * pitch
+    d, i, y, x = torch.meshgrid(*(torch.arange(n) for n in (2, Q, p.ny, p.nx)), indexing="ij")
+    idx = ((d * p.ny + y) * Q + i) * pitch + x
+    assert torch.equal(raw[idx.reshape(-1)].reshape(X.shape), X)
+    s.close()
+
+
 @pytest.mark.parametrize("storage", ("f64", "f32", "bf16_dev", "f32_dev"))
 def test_step_from_matches_step(storage):
     """dvbm_step_from(src, dst) computes the same step as dvbm_step and leaves the handle's state alone."""
