@@ -510,7 +510,8 @@ def test_largest_grids_sampled():
 def test_largest_grid_fp64_sampled():
     """4608 x 4608 in float64: one distribution takes 3.96 GiB, near the 4 GiB
     limit of the 32-bit load offsets; AUTO takes the column sweep, whose stores
-    go through one buffer resource per plane."""
+    go through one buffer resource per buffer row (the Q planes of one
+    distribution at one y)."""
     n = 4608
     print(f"[largest grid fp64] {n}x{n}", flush=True)
     wl = smooth_random(n, n, seed=22, amp_T=0.05)
